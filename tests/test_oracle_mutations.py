@@ -1,0 +1,57 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case copies the oracle to a temporary directory, plants one mistake in the
+copy (a dropped term, a wrong sign, index or divisor, a transposed operand),
+and checks that the oracle pin tests fail on it.  Nothing outside the temporary
+copy is modified.
+"""
+
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PIN_TESTS = ["test_oracle_dft.py", "test_oracle_variance.py", "test_oracle_update.py", "test_oracle_rng.py"]
+
+MUTANTS = [
+    ("enkf.py", "sum(axis=0) / (N - 1)", "sum(axis=0) / N"),
+    ("enkf.py", "0.0, c_hat / safe)", "0.0, R_spec / safe)"),
+    ("enkf.py", "(d_hat[None] + e_hat - u_hat)", "(d_hat[None] - e_hat - u_hat)"),
+    ("enkf.py", "(a + 1j * b) / np.sqrt(2.0))", "(a + 1j * b))"),
+    ("enkf.py", "np.where(mirrored, np.conj(zk), zk)", "zk"),
+    ("enkf.py", "np.where(mirrored, ny - ky, ky)", "ky"),
+    ("enkf.py", "if k % 2 == 0 else (words[2], words[3])", "if True else None"),
+    ("enkf.py", "dev = ens - ens.mean(axis=0, keepdims=True)\n    c = np.empty", "dev = ens\n    c = np.empty"),
+    ("enkf.py", "(x[:, None] - x[None, :]) % nx]", "(x[None, :] - x[:, None]) % nx]"),
+    ("dft.py", "ang = (2.0 * np.pi / m)", "ang = (-2.0 * np.pi / m)"),
+    ("dft.py", "np.conj(S[..., ky, nx - kx])", "S[..., ky, nx - kx]"),
+    ("dft.py", "u @ wx.real + 1j * (u @ wx.imag)", "u @ wx.real - 1j * (u @ wx.imag)"),
+    ("dft.py", "ky = (-np.arange(ny)) % ny", "ky = np.arange(ny)"),
+    ("dft.py", "(dft_matrix(ny, +1) @ full @ dft_matrix(nx, +1))", "(dft_matrix(ny, -1) @ full @ dft_matrix(nx, +1))"),
+    ("philox.py", "hi1 ^ x[1] ^ k0, lo1, hi0 ^ x[3] ^ k1", "hi1 ^ x[1] ^ k1, lo1, hi0 ^ x[3] ^ k0"),
+    ("philox.py", "np.sqrt(-2.0 * np.log(u1))", "np.sqrt(-1.0 * np.log(u1))"),
+    ("philox.py", "ang = 2.0 * np.pi * u2", "ang = np.pi * u2"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("fname,before,after", MUTANTS, ids=[f"{m[0]}:{m[2][:24]}" for m in MUTANTS])
+def test_pin_suite_catches_mutant(tmp_path, fname, before, after):
+    for sub in ("oracle", "tests"):
+        shutil.copytree(os.path.join(ROOT, sub), tmp_path / sub,
+                        ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutations.py"))
+    pkg = tmp_path / "paper_1001_1588_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_1001_1588_amd", "twin.py"), pkg / "twin.py")
+    (pkg / "__init__.py").write_text("")
+    target = tmp_path / "oracle" / fname
+    src = target.read_text()
+    assert before in src, "mutation anchor not found; update the mutant list"
+    target.write_text(src.replace(before, after, 1))
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          *[os.path.join("tests", t) for t in PIN_TESTS]],
+                         cwd=tmp_path, capture_output=True, text=True, timeout=600)
+    assert res.returncode != 0, "mutant survived the oracle pin tests:\n" + res.stdout[-2000:]
