@@ -1,0 +1,179 @@
+"""Throughput of the FFT EnKF analysis step on one MI355X.
+
+One step = one full analysis (sweeps 1-3: forward transforms, spectral
+statistics, gain, perturbations, update, inverse transforms) of the workload
+  large2048: periodic 2048 x 2048 grid, N = 20 members, float32, power-law
+  spectrum |k|^-3 (k != 0), R = 0.05 I given as an R_spec array,
+with all inputs resident in HBM before the timed region.
+
+Prints one JSON line: member-gridpoints analysed per second, the roofline of the
+dominant sweep (its algorithmic bytes per launch over its average HIP-event
+duration, against 8 TB/s), and the float64 CPU oracle timed on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+class HipEvents:
+    """Minimal hipEvent_t wrapper on the HIP runtime torch has loaded."""
+
+    def __init__(self):
+        self.h = ctypes.CDLL("libamdhip64.so")
+        self.h.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.h.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self) -> int:
+        ev = ctypes.c_void_p()
+        if self.h.hipEventCreate(ctypes.byref(ev)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return ev.value
+
+    def elapsed_ms(self, a: int, b: int) -> float:
+        ms = ctypes.c_float()
+        if self.h.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(a), ctypes.c_void_p(b)) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def destroy(self, ev: int) -> None:
+        self.h.hipEventDestroy(ctypes.c_void_p(ev))
+
+
+def sweep_bytes(N: int, ny: int, nx: int, s: int, rspec_array: bool) -> dict:
+    """Algorithmic bytes per launch of each sweep: its inputs read once and its
+    outputs written once (measurement section)."""
+    n = ny * nx
+    half = ny * (nx // 2 + 1) * 2 * s          # one complex half spectrum
+    rs = ny * (nx // 2 + 1) * s if rspec_array else 0
+    return {
+        "sweep1": (N + 1) * n * s + (N + 1) * half,
+        "sweep2": (N + 1) * half + rs + N * half,
+        "sweep3": N * half + N * n * s,
+        "path": (N + 1) * n * s + rs + N * n * s,  # members + d + R_spec in, members out
+    }
+
+
+def cpu_baseline(tw, members: int) -> dict:
+    from threadpoolctl import threadpool_info
+
+    from oracle import enkf
+
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    ens = tw.ens[:members]
+    t0 = time.perf_counter()
+    enkf.analyze(ens, tw.data, tw.R_spec, tw.seed)
+    dt = time.perf_counter() - t0
+    ny, nx = tw.data.shape
+    return {"value": members * ny * nx / dt, "unit": "member-gridpoints/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"float64 oracle (matrix DFT, numpy/OpenBLAS) on the full {ny}x{nx} grid, "
+                      f"{members} of the {tw.ens.shape[0]} members plus d, one analysis, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rspec", choices=["array", "scalar"], default="array")
+    ap.add_argument("--cpu-members", type=int, default=20, help="members in the CPU oracle sample (0 = skip)")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the analysis runs on a single MI355X in this build "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1001_1588_amd import _lib, twin
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1001_1588_amd import build as _build
+        _build.build()
+
+    dev = torch.device("cuda:0")
+    tw = twin.workload("large2048", seed=args.seed)
+    N, ny, nx = tw.ens.shape
+    ens = torch.from_numpy(tw.ens).to(dev)
+    data = torch.from_numpy(tw.data).to(dev)
+    R = torch.from_numpy(tw.R_spec).to(dev) if args.rspec == "array" else float(tw.r)
+    ws = torch.empty(_lib.workspace_bytes(N, ny, nx, torch.float32), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(ens)
+
+    for _ in range(args.warmup):
+        _lib.analyze(ens, data, R, tw.seed, out=out, workspace=ws)
+    torch.cuda.synchronize()
+
+    hip = HipEvents()
+    evs = [[hip.create() for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        _lib.profile_events(evs[s])
+        _lib.analyze(ens, data, R, tw.seed + s, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    per = np.array([[hip.elapsed_ms(e[i], e[i + 1]) for i in range(3)] for e in evs])  # [steps, 3]
+    gpu_span_ms = hip.elapsed_ms(evs[0][0], evs[-1][3])
+    for e in evs:
+        for x in e:
+            hip.destroy(x)
+
+    ms_per_step = 1e3 * wall / args.steps
+    mgp = N * ny * nx
+    value = mgp * args.steps / wall
+    b = sweep_bytes(N, ny, nx, 4, args.rspec == "array")
+    avg = per.mean(axis=0)
+    names = ["sweep1", "sweep2", "sweep3"]
+    dom = int(np.argmax(avg))
+    achieved = b[names[dom]] / (avg[dom] * 1e-3) / 1e9
+    result = {
+        "metric": "member-gridpoints analyzed/sec",
+        "value": value,
+        "unit": "member-gridpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "large2048: periodic 2048x2048 grid, N=20 members, float32, spectrum |k|^-3, "
+                               f"R=0.05 I ({'R_spec array' if args.rspec == 'array' else 'scalar r'})",
+                   "grid": [ny, nx], "members": N, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": names[dom]},
+        "sweep_ms": {names[i]: float(avg[i]) for i in range(3)},
+        "sweep_hbm_frac": {names[i]: b[names[i]] / (avg[i] * 1e-3) / 1e9 / HBM_PEAK_GBS for i in range(3)},
+        "path_bytes_per_step": b["path"],
+        "path_hbm_frac": b["path"] / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "gpu_event_ms_per_step": gpu_span_ms / args.steps,
+    }
+    if args.cpu_members > 0:
+        result["cpu_baseline"] = cpu_baseline(tw, min(args.cpu_members, N))
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,133 @@
+/*
+ * fftenkf.h -- C ABI of the FFT EnKF analysis step on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the FFT EnKF of Mandel, Beezley and Kondratenko, Section 2.1,
+ * for one block with H = I (the whole state observed) and a stationary data
+ * error covariance R:
+ *
+ *   step 1   u_hat_k = F u_k for each of the N forecast members, d_hat = F d;
+ *   eq. (2)  c_hat_i = 1/(N-1) sum_k |u_hat_ik - mean_k u_hat_ik|^2;
+ *   eq. (3)  u_hat_k^a = u_hat_k + c_hat (c_hat + R_spec)^-1 (d_hat + e_hat_k - u_hat_k),
+ *            entry by entry (R = r I gives R_spec = r everywhere);
+ *   then     u_k^a = F^-1 u_hat_k^a.
+ *
+ * F is the 2D DFT of a periodic grid, normalised to be unitary, so c_hat and
+ * R_spec are both eigenvalues of stationary covariances and the result does not
+ * depend on how the FFTs are scaled internally.  The perturbations e_k ~ N(0, R)
+ * of eq. (1) are drawn in the frequency domain, e_hat_k = sqrt(R_spec) z_hat_k,
+ * with z_hat_k distributed as the unitary DFT of real white noise:
+ *   - generic bins: (a + i b) / sqrt(2);
+ *   - the four self-conjugate bins (ky in {0, ny/2}, kx in {0, nx/2}): a;
+ *   - bins in the kx = 0 and kx = nx/2 columns with ky > ny/2: the conjugate of
+ *     the value drawn for (ny - ky, kx).
+ * (a, b) = Box-Muller(u1, u2) with u = (2 * (w >> 9) + 1) * 2^-24 for words w of
+ * Philox4x32-10 (Salmon et al., SC'11), key = (seed mod 2^32, seed div 2^32),
+ * counter = (gy * (nx/2 + 1) + gx, k div 2, 0, 0) for the generating bin
+ * (gy, gx); member k takes words (x0, x1) if k is even, (x2, x3) if odd.
+ * The gain is 0 where c_hat + R_spec is below the smallest normal number of the
+ * working precision (no spread and no data error: no update).
+ *
+ * Layouts (row-major, x fastest):
+ *   members / out : [N][ny][nx]  real, dtype        (device memory)
+ *   data          : [ny][nx]     real, dtype        (device memory)
+ *   R_spec        : [ny][nx/2+1] real, dtype        (device memory), or NULL
+ *                   to use ens->r_scalar for every bin.  Values must be >= 0
+ *                   and finite; in the kx = 0 and kx = nx/2 columns R_spec must
+ *                   be even in ky (it is the spectrum of a real symmetric R).
+ * All device pointers must be 16-byte aligned; the workspace 256-byte aligned.
+ *
+ * Ownership: the caller owns every buffer.  The library keeps only per-device
+ * twiddle tables in static device memory (no allocation).
+ *
+ * Errors: arguments are validated before anything is enqueued; on any error
+ * nothing is written and the return value is negative.  NaN or Inf in the
+ * numeric inputs is not checked and propagates.  No C++ exception crosses
+ * this interface.  fftenkf_last_error() gives a message for the calling thread.
+ *
+ * Concurrency: calls are asynchronous on ens->stream, like a kernel launch.
+ * Two calls sharing a workspace must be ordered on one stream.
+ */
+#ifndef FFTENKF_H
+#define FFTENKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FFTENKF_OK = 0,
+  FFTENKF_EINVAL = -1,        /* null pointer, N < 2, bad dtype, aliasing, alignment, small workspace */
+  FFTENKF_EUNSUPPORTED = -2,  /* grid not a power of two in [8, 4096], or N beyond the supported range */
+  FFTENKF_EDEVICE = -3,       /* a HIP runtime call failed, or a pointer is not device memory */
+  FFTENKF_ENOMEM = -4         /* reserved: the library allocates nothing today */
+};
+
+enum { FFTENKF_F32 = 0, FFTENKF_F64 = 1 };
+
+typedef struct fftenkf_ens {
+  int32_t n_members;      /* N, 2 <= N <= fftenkf_max_members(dtype) */
+  int32_t ny, nx;         /* grid, each a power of two in [8, 4096] */
+  int32_t dtype;          /* FFTENKF_F32 or FFTENKF_F64: members, data, R_spec and out */
+  const void* members;    /* device [N][ny][nx] forecast ensemble u_k */
+  void* workspace;        /* device scratch of at least fftenkf_workspace_bytes(...) bytes */
+  size_t workspace_bytes; /* size of workspace in bytes */
+  void* stream;           /* hipStream_t to enqueue on; NULL means the default stream */
+  double r_scalar;        /* R = r_scalar * I when R_spec is NULL */
+} fftenkf_ens;
+
+/*
+ * One FFT EnKF analysis, eq. (3) with the estimator of eq. (2) (Section 2.1).
+ * out may equal ens->members (in place); any other overlap of out, data,
+ * R_spec, members and workspace is FFTENKF_EINVAL.  Enqueued on ens->stream;
+ * synchronise the stream before reading out.  Same inputs and seed give
+ * bitwise-identical output.
+ */
+int fftenkf_analyze(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed, void* out);
+
+/* Bytes of workspace fftenkf_analyze needs: (N+1) spectra of ny*(nx/2+1) complex
+ * values plus one ny*(nx/2+1) real plane, rounded up to 256; 0 if the shape is invalid. */
+size_t fftenkf_workspace_bytes(int n_members, int ny, int nx, int dtype);
+
+/* Largest N the analysis supports for a dtype. */
+int fftenkf_max_members(int dtype);
+
+/* Static description of a status code, and the last error message of this thread. */
+const char* fftenkf_strerror(int status);
+const char* fftenkf_last_error(void);
+
+/*
+ * Test-only exports.  They run the same kernels as fftenkf_analyze.
+ *
+ * fftenkf_debug_spectra: after the forward transforms, writes per bin the
+ *   estimator c_hat of eq. (2) and the gain c_hat/(c_hat + R_spec) of eq. (3)
+ *   (device [ny][nx/2+1] real each), and, if spectra is not NULL, the unitary
+ *   half spectra of the N members followed by d (device [N+1][ny][nx/2+1]
+ *   complex, interleaved re/im).  ens->members is not modified.
+ * fftenkf_debug_perturb: writes e_hat_k (device [N][ny][nx/2+1] complex), the
+ *   unitary-scale spectral perturbations drawn for `seed` (Section 2, eq. (1)).
+ * fftenkf_debug_fail_next: the next validated call of this thread returns
+ *   `status` without enqueuing anything (forces the device-failure path).
+ */
+int fftenkf_debug_spectra(const fftenkf_ens* ens, const void* data, const void* R_spec, void* c_hat,
+                          void* gain, void* spectra);
+int fftenkf_debug_perturb(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed,
+                          void* e_hat);
+void fftenkf_debug_fail_next(int status);
+
+/*
+ * Profiling hook for the calling thread: with n == 4, the next fftenkf_analyze
+ * records events[0] before sweep 1, events[1] between sweeps 1 and 2, events[2]
+ * between sweeps 2 and 3 and events[3] after sweep 3, on ens->stream (each a
+ * hipEvent_t created by the caller), then forgets them.  n == 0 clears it.
+ * Returns FFTENKF_EINVAL for any other n or a NULL array.
+ */
+int fftenkf_profile_events(void* const* events, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTENKF_H */

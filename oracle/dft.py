@@ -50,7 +50,9 @@ def rdft2(u: np.ndarray, method: str = "matmul") -> np.ndarray:
         raise ValueError(method)
     wx = dft_matrix(nx)[:, :nh]                  # [x, kx]
     wy = dft_matrix(ny)                          # [ky, y]
-    along_x = u @ wx.real + 1j * (u @ wx.imag)   # [..., y, kx]
+    # contiguous real and imaginary parts, so the products go to BLAS
+    wx_re, wx_im = np.ascontiguousarray(wx.real), np.ascontiguousarray(wx.imag)
+    along_x = u @ wx_re + 1j * (u @ wx_im)       # [..., y, kx]
     return (wy @ along_x) * scale                # [..., ky, kx]
 
 

@@ -1,0 +1,174 @@
+"""ctypes binding of libfftenkf.so (include/fftenkf.h): argument marshalling only.
+
+Every step of the analysis runs in the HIP kernels behind the C ABI.  PyTorch
+supplies device memory and the current stream.  If the library has not been
+built, or the call fails, a RuntimeError is raised; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Union
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfftenkf.so")
+
+OK, EINVAL, EUNSUPPORTED, EDEVICE, ENOMEM = 0, -1, -2, -3, -4
+F32, F64 = 0, 1
+
+
+class Ens(ctypes.Structure):
+    """Mirror of struct fftenkf_ens."""
+
+    _fields_ = [
+        ("n_members", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("members", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+        ("r_scalar", ctypes.c_double),
+    ]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+EXPORTS = {
+    "fftenkf_analyze": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "fftenkf_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "fftenkf_max_members": (ctypes.c_int, [ctypes.c_int]),
+    "fftenkf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "fftenkf_last_error": (ctypes.c_char_p, []),
+    "fftenkf_debug_spectra": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "fftenkf_debug_perturb": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                             ctypes.c_void_p]),
+    "fftenkf_debug_fail_next": (None, [ctypes.c_int]),
+    "fftenkf_profile_events": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfftenkf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1001_1588_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(status: int, what: str) -> None:
+    if status != OK:
+        msg = lib().fftenkf_last_error().decode(errors="replace")
+        raise RuntimeError(f"{what} failed: {lib().fftenkf_strerror(status).decode()} ({status}): {msg}")
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t.dtype}: float32 or float64")
+
+
+def workspace_bytes(n_members: int, ny: int, nx: int, dtype: torch.dtype) -> int:
+    code = F32 if dtype == torch.float32 else F64
+    return int(lib().fftenkf_workspace_bytes(n_members, ny, nx, code))
+
+
+def max_members(dtype: torch.dtype) -> int:
+    return int(lib().fftenkf_max_members(F32 if dtype == torch.float32 else F64))
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _make_ens(ens: torch.Tensor, workspace: Optional[torch.Tensor], r_scalar: float) -> tuple:
+    if ens.dim() != 3:
+        raise ValueError("ens must be [N, ny, nx]")
+    if not ens.is_cuda:
+        raise ValueError("ens must be a device tensor")
+    if not ens.is_contiguous():
+        raise ValueError("ens must be contiguous")
+    N, ny, nx = ens.shape
+    need = workspace_bytes(N, ny, nx, ens.dtype)
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=ens.device)
+    e = Ens(n_members=N, ny=ny, nx=nx, dtype=_dtype_code(ens), members=ens.data_ptr(),
+            workspace=workspace.data_ptr(), workspace_bytes=workspace.numel() * workspace.element_size(),
+            stream=torch.cuda.current_stream(ens.device).cuda_stream, r_scalar=float(r_scalar))
+    return e, workspace
+
+
+def _rspec(R_spec: Union[torch.Tensor, float, None]):
+    if R_spec is None or isinstance(R_spec, (int, float)):
+        return None, float(R_spec or 0.0)
+    return R_spec, 0.0
+
+
+def analyze(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, float], seed: int,
+            out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One FFT EnKF analysis (eq. (3) with eq. (2)); returns the analysis ensemble.
+
+    R_spec is a [ny, nx//2+1] tensor of R's eigenvalues or a float r (R = r I).
+    out may be ens itself (in place).  Enqueued on the current stream."""
+    R_t, r = _rspec(R_spec)
+    e, ws = _make_ens(ens, workspace, r)
+    if out is None:
+        out = torch.empty_like(ens)
+    st = lib().fftenkf_analyze(ctypes.byref(e), data.data_ptr(), _ptr(R_t), ctypes.c_uint64(seed & (2**64 - 1)),
+                               out.data_ptr())
+    _check(st, "fftenkf_analyze")
+    return out
+
+
+def debug_spectra(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, float],
+                  with_spectra: bool = True):
+    """(c_hat, gain, spectra) per bin, spectra = unitary half spectra of members then d."""
+    R_t, r = _rspec(R_spec)
+    e, ws = _make_ens(ens, None, r)
+    N, ny, nx = ens.shape
+    nh = nx // 2 + 1
+    c_hat = torch.empty((ny, nh), dtype=ens.dtype, device=ens.device)
+    gain = torch.empty_like(c_hat)
+    spec = torch.empty((N + 1, ny, nh, 2), dtype=ens.dtype, device=ens.device) if with_spectra else None
+    st = lib().fftenkf_debug_spectra(ctypes.byref(e), data.data_ptr(), _ptr(R_t), c_hat.data_ptr(), gain.data_ptr(),
+                                     _ptr(spec))
+    _check(st, "fftenkf_debug_spectra")
+    return c_hat, gain, spec
+
+
+def debug_perturb(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, float], seed: int):
+    """Unitary spectral perturbations e_hat [N, ny, nx//2+1, 2] drawn for `seed`."""
+    R_t, r = _rspec(R_spec)
+    e, ws = _make_ens(ens, None, r)
+    N, ny, nx = ens.shape
+    out = torch.empty((N, ny, nx // 2 + 1, 2), dtype=ens.dtype, device=ens.device)
+    st = lib().fftenkf_debug_perturb(ctypes.byref(e), data.data_ptr(), _ptr(R_t),
+                                     ctypes.c_uint64(seed & (2**64 - 1)), out.data_ptr())
+    _check(st, "fftenkf_debug_perturb")
+    return out
+
+
+def debug_fail_next(status: int) -> None:
+    lib().fftenkf_debug_fail_next(status)
+
+
+def profile_events(events) -> None:
+    """Record the 4 given hipEvent_t handles around the sweeps of the next analyze."""
+    if not events:
+        _check(lib().fftenkf_profile_events(None, 0), "fftenkf_profile_events")
+        return
+    arr = (ctypes.c_void_p * len(events))(*events)
+    _check(lib().fftenkf_profile_events(arr, len(events)), "fftenkf_profile_events")

@@ -1,0 +1,385 @@
+// C ABI of the FFT EnKF analysis: argument validation, planning and dispatch
+// of the three sweeps onto the caller's stream.  See include/fftenkf.h.
+#include "fftenkf.h"
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+
+#include "kernels.hpp"
+
+namespace fftenkf {
+
+hipError_t launch_k2_f32_n4(const K2Args&, hipStream_t);
+hipError_t launch_k2_f32_n8(const K2Args&, hipStream_t);
+hipError_t launch_k2_f32_n12(const K2Args&, hipStream_t);
+hipError_t launch_k2_f32_n16(const K2Args&, hipStream_t);
+hipError_t launch_k2_f32_n20(const K2Args&, hipStream_t);
+hipError_t launch_k2_f32_n24(const K2Args&, hipStream_t);
+hipError_t launch_k2_f64_n4(const K2Args&, hipStream_t);
+hipError_t launch_k2_f64_n8(const K2Args&, hipStream_t);
+
+int k2_member_bucket(int dtype, int N) {
+  static const int f32[] = {4, 8, 12, 16, 20, 24};
+  static const int f64[] = {4, 8};
+  const int* b = dtype == FFTENKF_F32 ? f32 : f64;
+  const int nb = dtype == FFTENKF_F32 ? 6 : 2;
+  for (int i = 0; i < nb; ++i)
+    if (N <= b[i]) return b[i];
+  return 0;
+}
+
+hipError_t launch_k2_f32(const K2Args& a, hipStream_t s) {
+  switch (k2_member_bucket(FFTENKF_F32, a.N)) {
+    case 4: return launch_k2_f32_n4(a, s);
+    case 8: return launch_k2_f32_n8(a, s);
+    case 12: return launch_k2_f32_n12(a, s);
+    case 16: return launch_k2_f32_n16(a, s);
+    case 20: return launch_k2_f32_n20(a, s);
+    case 24: return launch_k2_f32_n24(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_k2_f64(const K2Args& a, hipStream_t s) {
+  switch (k2_member_bucket(FFTENKF_F64, a.N)) {
+    case 4: return launch_k2_f64_n4(a, s);
+    case 8: return launch_k2_f64_n8(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+namespace {
+
+thread_local std::string t_last_error;
+thread_local int t_fail_next = 0;
+thread_local hipEvent_t t_events[4] = {nullptr, nullptr, nullptr, nullptr};
+thread_local bool t_events_on = false;
+
+hipError_t mark(int i, hipStream_t s) {
+  if (!t_events_on) return hipSuccess;
+  return hipEventRecord(t_events[i], s);
+}
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  t_last_error = buf;
+  return code;
+}
+
+bool pow2_in_range(int v) { return v >= 8 && v <= 4096 && (v & (v - 1)) == 0; }
+
+size_t dsize(int dtype) { return dtype == FFTENKF_F64 ? 8 : 4; }
+
+// Grid factorisation ny = R * L and the unit shape of the spectral sweep.
+struct Plan {
+  int R, L, P, C, units_main, units_total;
+  size_t main_elems, nyq_elems;  // complex elements of the two workspace regions
+  size_t ws_bytes;
+};
+
+int rows_per_tile(int dtype, int nx) {
+  if (dtype == FFTENKF_F32) return nx <= 2048 ? 16 : 8;
+  return nx <= 2048 ? 8 : 4;
+}
+
+Plan make_plan(int N, int ny, int nx, int dtype) {
+  Plan p{};
+  const int rmax = rows_per_tile(dtype, nx);
+  p.R = ny < rmax ? ny : rmax;
+  p.L = ny / p.R;
+  p.P = k2_points(p.L);
+  const int tf2 = p.L / p.P;
+  const int nxh = nx / 2;
+  int c = k2_threads_target / tf2;
+  if (c > nxh) c = nxh;
+  if (c < 1) c = 1;
+  p.C = c;
+  p.units_main = p.R * (nxh / c);
+  p.units_total = p.units_main + (p.R + c - 1) / c;
+  const size_t nf = (size_t)N + 1;
+  p.main_elems = nf * (size_t)ny * (size_t)nxh;
+  p.nyq_elems = nf * (size_t)ny;
+  const size_t cplx = 2 * dsize(dtype);
+  size_t bytes = (p.main_elems + p.nyq_elems) * cplx + (size_t)ny * (size_t)(nxh + 1) * dsize(dtype);
+  p.ws_bytes = (bytes + 255) / 256 * 256;
+  return p;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+bool misaligned(const void* p, size_t a) { return ((uintptr_t)p % a) != 0; }
+
+// Shape, dtype, N and workspace checks common to every entry point.
+int validate_shape(const fftenkf_ens* e, Plan* plan) {
+  if (e == nullptr) return fail(FFTENKF_EINVAL, "ens is NULL");
+  if (e->dtype != FFTENKF_F32 && e->dtype != FFTENKF_F64) return fail(FFTENKF_EINVAL, "dtype %d is not 0 (f32) or 1 (f64)", e->dtype);
+  if (e->n_members < 2) return fail(FFTENKF_EINVAL, "n_members = %d, eq. (2) needs N >= 2", e->n_members);
+  if (!pow2_in_range(e->ny) || !pow2_in_range(e->nx))
+    return fail(FFTENKF_EUNSUPPORTED, "grid %d x %d: each side must be a power of two in [8, 4096]", e->ny, e->nx);
+  if (k2_member_bucket(e->dtype, e->n_members) == 0)
+    return fail(FFTENKF_EUNSUPPORTED, "n_members = %d exceeds %d for this dtype", e->n_members, fftenkf_max_members(e->dtype));
+  *plan = make_plan(e->n_members, e->ny, e->nx, e->dtype);
+  if (e->members == nullptr) return fail(FFTENKF_EINVAL, "members is NULL");
+  if (e->workspace == nullptr) return fail(FFTENKF_EINVAL, "workspace is NULL");
+  if (e->workspace_bytes < plan->ws_bytes)
+    return fail(FFTENKF_EINVAL, "workspace of %zu bytes, %zu needed", e->workspace_bytes, plan->ws_bytes);
+  if (misaligned(e->members, 16)) return fail(FFTENKF_EINVAL, "members is not 16-byte aligned");
+  if (misaligned(e->workspace, 256)) return fail(FFTENKF_EINVAL, "workspace is not 256-byte aligned");
+  return FFTENKF_OK;
+}
+
+// Every pointer must be device memory of the current device.
+int check_device_pointer(const void* p, const char* what, int dev) {
+  hipPointerAttribute_t attr;
+  memset(&attr, 0, sizeof(attr));
+  const hipError_t err = hipPointerGetAttributes(&attr, p);
+  if (err != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FFTENKF_EDEVICE, "%s: not a HIP allocation (%s)", what, hipGetErrorString(err));
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(FFTENKF_EINVAL, "%s is not device memory", what);
+  if (attr.device != dev) return fail(FFTENKF_EINVAL, "%s lives on device %d, current device is %d", what, attr.device, dev);
+  return FFTENKF_OK;
+}
+
+struct Ptr {
+  const void* p;
+  size_t bytes;
+  const char* name;
+};
+
+int check_pointers(const Ptr* ptrs, int n) {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "hipGetDevice: %s", hipGetErrorString(err));
+  for (int i = 0; i < n; ++i)
+    if (ptrs[i].p != nullptr) {
+      const int st = check_device_pointer(ptrs[i].p, ptrs[i].name, dev);
+      if (st != FFTENKF_OK) return st;
+    }
+  return FFTENKF_OK;
+}
+
+bool log_enabled() {
+  static int on = -1;
+  if (on < 0) {
+    const char* v = getenv("FFTENKF_LOG");
+    on = (v != nullptr && v[0] == '1') ? 1 : 0;
+  }
+  return on == 1;
+}
+
+// Enqueue sweeps 1 and 2 (mode) and, for an analysis, sweep 3.
+int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_spec, uint64_t seed, void* out,
+        int mode, void* dbg_chat, void* dbg_gain, void* dbg_spec, void* dbg_e) {
+  if (t_fail_next != 0) {
+    const int st = t_fail_next;
+    t_fail_next = 0;
+    return fail(st, "failure forced by fftenkf_debug_fail_next");
+  }
+  hipStream_t stream = static_cast<hipStream_t>(e->stream);
+  const void* tab = nullptr;
+  hipError_t err = twiddle_table(e->dtype, &tab);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
+  const size_t cplx = 2 * dsize(e->dtype);
+  char* ws = static_cast<char*>(e->workspace);
+  void* ws_main = ws;
+  void* ws_nyq = ws + plan.main_elems * cplx;
+  if (log_enabled())
+    fprintf(stderr, "fftenkf: N=%d grid %dx%d dtype=%d R=%d L=%d C=%d units=%d mode=%d\n", e->n_members, e->ny,
+            e->nx, e->dtype, plan.R, plan.L, plan.C, plan.units_total, mode);
+
+  const bool profiled = t_events_on && mode == K2_ANALYZE;
+  if (!profiled) t_events_on = false;
+  err = mark(0, stream);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "profile event: %s", hipGetErrorString(err));
+  K1Args a1{e->members, data, e->n_members, e->ny, e->nx, plan.R, plan.L, ws_main, ws_nyq, tab};
+  err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
+  if (err == hipSuccess) err = mark(1, stream);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 1 launch: %s", hipGetErrorString(err));
+
+  K2Args a2{};
+  a2.ws_main = ws_main;
+  a2.ws_nyq = ws_nyq;
+  a2.R_spec = R_spec;
+  a2.r_scalar = e->r_scalar;
+  a2.N = e->n_members;
+  a2.ny = e->ny;
+  a2.nx = e->nx;
+  a2.R = plan.R;
+  a2.L = plan.L;
+  a2.C = plan.C;
+  a2.units_main = plan.units_main;
+  a2.units_total = plan.units_total;
+  a2.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  a2.key1 = (uint32_t)(seed >> 32);
+  a2.mode = mode;
+  a2.dbg_chat = dbg_chat;
+  a2.dbg_gain = dbg_gain;
+  a2.dbg_spec = dbg_spec;
+  a2.dbg_e = dbg_e;
+  a2.tab = tab;
+  err = e->dtype == FFTENKF_F32 ? launch_k2_f32(a2, stream) : launch_k2_f64(a2, stream);
+  if (err == hipSuccess) err = mark(2, stream);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 2 launch: %s", hipGetErrorString(err));
+  if (mode != K2_ANALYZE) return FFTENKF_OK;
+
+  K3Args a3{ws_main, ws_nyq, e->n_members, e->ny, e->nx, plan.R, plan.L, out, tab};
+  err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
+  if (err == hipSuccess) err = mark(3, stream);
+  t_events_on = false;
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 3 launch: %s", hipGetErrorString(err));
+  return FFTENKF_OK;
+}
+
+}  // namespace
+}  // namespace fftenkf
+
+using namespace fftenkf;
+
+extern "C" {
+
+int fftenkf_max_members(int dtype) {
+  if (dtype == FFTENKF_F32) return kMaxMembersF32;
+  if (dtype == FFTENKF_F64) return kMaxMembersF64;
+  return 0;
+}
+
+size_t fftenkf_workspace_bytes(int n_members, int ny, int nx, int dtype) {
+  if ((dtype != FFTENKF_F32 && dtype != FFTENKF_F64) || n_members < 2 || !pow2_in_range(ny) || !pow2_in_range(nx))
+    return 0;
+  return make_plan(n_members, ny, nx, dtype).ws_bytes;
+}
+
+const char* fftenkf_strerror(int status) {
+  switch (status) {
+    case FFTENKF_OK: return "success";
+    case FFTENKF_EINVAL: return "invalid argument";
+    case FFTENKF_EUNSUPPORTED: return "unsupported shape";
+    case FFTENKF_EDEVICE: return "HIP device error";
+    case FFTENKF_ENOMEM: return "out of memory";
+    default: return "unknown status";
+  }
+}
+
+const char* fftenkf_last_error(void) { return t_last_error.c_str(); }
+
+void fftenkf_debug_fail_next(int status) { t_fail_next = status; }
+
+int fftenkf_profile_events(void* const* events, int n) {
+  if (n == 0) {
+    t_events_on = false;
+    return FFTENKF_OK;
+  }
+  if (n != 4 || events == nullptr) return fail(FFTENKF_EINVAL, "profile events: need an array of 4 events");
+  for (int i = 0; i < 4; ++i) {
+    if (events[i] == nullptr) return fail(FFTENKF_EINVAL, "profile events: event %d is NULL", i);
+    t_events[i] = static_cast<hipEvent_t>(events[i]);
+  }
+  t_events_on = true;
+  return FFTENKF_OK;
+}
+
+int fftenkf_analyze(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed, void* out) {
+  try {
+    Plan plan;
+    int st = validate_shape(e, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (data == nullptr) return fail(FFTENKF_EINVAL, "data is NULL");
+    if (out == nullptr) return fail(FFTENKF_EINVAL, "out is NULL");
+    if (misaligned(data, 16) || misaligned(out, 16) || (R_spec != nullptr && misaligned(R_spec, 16)))
+      return fail(FFTENKF_EINVAL, "data, R_spec and out must be 16-byte aligned");
+    if (R_spec == nullptr && !(e->r_scalar >= 0.0))
+      return fail(FFTENKF_EINVAL, "r_scalar must be >= 0 when R_spec is NULL");
+    const size_t s = dsize(e->dtype);
+    const size_t field = (size_t)e->ny * e->nx * s;
+    const size_t ens_b = field * e->n_members;
+    const size_t rs_b = (size_t)e->ny * (e->nx / 2 + 1) * s;
+    const Ptr ptrs[] = {{e->members, ens_b, "members"},
+                        {data, field, "data"},
+                        {R_spec, rs_b, "R_spec"},
+                        {out, ens_b, "out"},
+                        {e->workspace, plan.ws_bytes, "workspace"}};
+    const int np = 5;
+    for (int i = 0; i < np; ++i)
+      for (int j = i + 1; j < np; ++j) {
+        if (ptrs[i].p == nullptr || ptrs[j].p == nullptr) continue;
+        const bool in_place = (i == 0 && j == 3 && ptrs[i].p == ptrs[j].p);
+        if (!in_place && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+      }
+    st = check_pointers(ptrs, np);
+    if (st != FFTENKF_OK) return st;
+    return run(e, plan, data, R_spec, seed, out, K2_ANALYZE, nullptr, nullptr, nullptr, nullptr);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+int fftenkf_debug_spectra(const fftenkf_ens* e, const void* data, const void* R_spec, void* c_hat, void* gain,
+                          void* spectra) {
+  try {
+    Plan plan;
+    int st = validate_shape(e, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (data == nullptr || c_hat == nullptr || gain == nullptr) return fail(FFTENKF_EINVAL, "data, c_hat and gain are required");
+    const size_t s = dsize(e->dtype);
+    const size_t plane = (size_t)e->ny * (e->nx / 2 + 1);
+    const Ptr ptrs[] = {{e->members, (size_t)e->ny * e->nx * s * e->n_members, "members"},
+                        {data, (size_t)e->ny * e->nx * s, "data"},
+                        {R_spec, plane * s, "R_spec"},
+                        {c_hat, plane * s, "c_hat"},
+                        {gain, plane * s, "gain"},
+                        {spectra, plane * 2 * s * (e->n_members + 1), "spectra"},
+                        {e->workspace, plan.ws_bytes, "workspace"}};
+    for (int i = 0; i < 7; ++i)
+      for (int j = i + 1; j < 7; ++j)
+        if (ptrs[i].p && ptrs[j].p && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+    st = check_pointers(ptrs, 7);
+    if (st != FFTENKF_OK) return st;
+    return run(e, plan, data, R_spec, 0, nullptr, K2_DEBUG_SPECTRA, c_hat, gain, spectra, nullptr);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+int fftenkf_debug_perturb(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed, void* e_hat) {
+  try {
+    Plan plan;
+    int st = validate_shape(e, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (data == nullptr || e_hat == nullptr) return fail(FFTENKF_EINVAL, "data and e_hat are required");
+    const size_t s = dsize(e->dtype);
+    const size_t plane = (size_t)e->ny * (e->nx / 2 + 1);
+    const Ptr ptrs[] = {{e->members, (size_t)e->ny * e->nx * s * e->n_members, "members"},
+                        {data, (size_t)e->ny * e->nx * s, "data"},
+                        {R_spec, plane * s, "R_spec"},
+                        {e_hat, plane * 2 * s * e->n_members, "e_hat"},
+                        {e->workspace, plan.ws_bytes, "workspace"}};
+    for (int i = 0; i < 5; ++i)
+      for (int j = i + 1; j < 5; ++j)
+        if (ptrs[i].p && ptrs[j].p && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+    st = check_pointers(ptrs, 5);
+    if (st != FFTENKF_OK) return st;
+    return run(e, plan, data, R_spec, seed, nullptr, K2_DEBUG_PERTURB, nullptr, nullptr, nullptr, e_hat);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,328 @@
+// Register/LDS FFT building blocks for gfx950 (wave64, 64 KiB-class LDS budgets).
+//
+// Conventions: forward transforms use W_m = exp(-2 pi i / m) and are
+// unnormalised; an inverse transform is computed as swap(FFT(swap(x))), where
+// swap exchanges real and imaginary parts (a register renaming, no arithmetic).
+//
+// A length-NFFT transform is spread over TF = NFFT / P threads holding P points
+// each.  Thread t always holds the elements {t + TF * i : 0 <= i < P}: that is
+// the input set of the first Stockham pass and the output set of the last, so
+// loads and stores of whole sequences are coalesced across threads, and between
+// passes the data is exchanged through LDS.  Pass s has radix RAD = min(P,
+// NFFT / NS), NS the product of the earlier radices (Stockham autosort, no bit
+// reversal).  Twiddles come from one table of W_4096^k (k < 4096) computed in
+// float64 on the host and rounded once; W_M^j = W_4096^(j * 4096 / M).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace fftenkf {
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B, B+S, ... < E.
+// Used wherever a register array is indexed, so the index is always constant.
+template <int B, int E, int S = 1, typename F>
+__host__ __device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + S, E, S>(f);
+  }
+}
+
+constexpr int kTwiddleN = 4096;
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+template <typename T> using V2 = typename vec2<T>::type;
+
+template <typename T> struct cx {
+  T re, im;
+};
+
+template <typename T> __host__ __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T> __host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __host__ __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T> __host__ __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T> __host__ __device__ __forceinline__ cx<T> swapri(cx<T> a) { return {a.im, a.re}; }
+// a * (-i)
+template <typename T> __host__ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.im, -a.re}; }
+// a * (+i)
+template <typename T> __host__ __device__ __forceinline__ cx<T> mul_pi(cx<T> a) { return {-a.im, a.re}; }
+
+template <typename T> __host__ __device__ __forceinline__ cx<T> from2(V2<T> v) { return {v.x, v.y}; }
+template <typename T> __host__ __device__ __forceinline__ V2<T> to2(cx<T> a) {
+  V2<T> v;
+  v.x = a.re;
+  v.y = a.im;
+  return v;
+}
+
+// cos and sin of 2 pi k / 16, k = 0..15 (forward twiddle W_16^k = c - i s).
+__host__ __device__ constexpr double kCos16(int k) {
+  return k == 0 ? 1.0 : k == 1 ? 0.92387953251128675613 : k == 2 ? 0.70710678118654752440
+       : k == 3 ? 0.38268343236508977173 : k == 4 ? 0.0 : k == 5 ? -0.38268343236508977173
+       : k == 6 ? -0.70710678118654752440 : k == 7 ? -0.92387953251128675613 : k == 8 ? -1.0
+       : k == 9 ? -0.92387953251128675613 : k == 10 ? -0.70710678118654752440
+       : k == 11 ? -0.38268343236508977173 : k == 12 ? 0.0 : k == 13 ? 0.38268343236508977173
+       : k == 14 ? 0.70710678118654752440 : 0.92387953251128675613;
+}
+__host__ __device__ constexpr double kSin16(int k) { return kCos16((k + 12) & 15); }  // sin x = cos(x - pi/2)
+
+// Forward twiddle W_R^k for R dividing 16, as a constant.
+template <typename T, int R>
+__host__ __device__ __forceinline__ cx<T> w_const(int k) {
+  const int j = ((k % R) + R) % R * (16 / R);
+  return cx<T>{T(kCos16(j)), T(-kSin16(j))};
+}
+
+// Multiply by the constant W_16^k, using the cheapest form for the special angles.
+template <typename T, int K>
+__host__ __device__ __forceinline__ cx<T> mul_w16(cx<T> a) {
+  constexpr int k = K & 15;
+  if constexpr (k == 0) return a;
+  else if constexpr (k == 4) return mul_mi(a);
+  else if constexpr (k == 8) return cx<T>{-a.re, -a.im};
+  else if constexpr (k == 12) return mul_pi(a);
+  else if constexpr (k == 2 || k == 6 || k == 10 || k == 14) {
+    constexpr T h = T(0.70710678118654752440);
+    cx<T> b = k == 2 ? a : k == 6 ? mul_mi(a) : k == 10 ? cx<T>{-a.re, -a.im} : mul_pi(a);
+    // b * (1 - i) / sqrt(2)
+    return cx<T>{(b.re + b.im) * h, (b.im - b.re) * h};
+  } else {
+    return a * cx<T>{T(kCos16(k)), T(-kSin16(k))};
+  }
+}
+
+// ---------------------------------------------------------------- small DFTs
+// In-place forward DFT of R points in natural order.
+template <typename T>
+__host__ __device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+  cx<T> s = a + b, d = a - b;
+  a = s;
+  b = d;
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void dft4(cx<T>& v0, cx<T>& v1, cx<T>& v2, cx<T>& v3) {
+  cx<T> t0 = v0 + v2, t1 = v0 - v2, t2 = v1 + v3, t3 = mul_mi(v1 - v3);
+  v0 = t0 + t2;
+  v2 = t0 - t2;
+  v1 = t1 + t3;
+  v3 = t1 - t3;
+}
+
+template <typename T, int R>
+__host__ __device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    dft2(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    o1 = mul_w16<T, 2>(o1);
+    o2 = mul_w16<T, 4>(o2);
+    o3 = mul_w16<T, 6>(o3);
+    v[0] = e0 + o0; v[4] = e0 - o0;
+    v[1] = e1 + o1; v[5] = e1 - o1;
+    v[2] = e2 + o2; v[6] = e2 - o2;
+    v[3] = e3 + o3; v[7] = e3 - o3;
+  } else if constexpr (R == 16) {
+    // n = n1 + 4 n2, k = k2 + 4 k1
+    cx<T> y[4][4];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+      y[n1][0] = v[n1]; y[n1][1] = v[n1 + 4]; y[n1][2] = v[n1 + 8]; y[n1][3] = v[n1 + 12];
+      dft4(y[n1][0], y[n1][1], y[n1][2], y[n1][3]);
+    }
+    y[1][1] = mul_w16<T, 1>(y[1][1]); y[1][2] = mul_w16<T, 2>(y[1][2]); y[1][3] = mul_w16<T, 3>(y[1][3]);
+    y[2][1] = mul_w16<T, 2>(y[2][1]); y[2][2] = mul_w16<T, 4>(y[2][2]); y[2][3] = mul_w16<T, 6>(y[2][3]);
+    y[3][1] = mul_w16<T, 3>(y[3][1]); y[3][2] = mul_w16<T, 6>(y[3][2]); y[3][3] = mul_w16<T, 9>(y[3][3]);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      cx<T> a = y[0][k2], b = y[1][k2], c = y[2][k2], d = y[3][k2];
+      dft4(a, b, c, d);
+      v[k2] = a; v[k2 + 4] = b; v[k2 + 8] = c; v[k2 + 12] = d;
+    }
+  } else {
+    static_assert(R == 1, "unsupported radix");
+  }
+}
+
+// Forward DFT of R real samples a[0..R-1]: V[k], k = 0..R/2 (V[0], V[R/2] real).
+// Uses one complex DFT of length R/2 on z[m] = a[2m] + i a[2m+1].
+template <typename T, int R>
+__host__ __device__ __forceinline__ void rdft(const T* a, cx<T>* V) {
+  constexpr int H = R / 2;
+  cx<T> z[H];
+#pragma unroll
+  for (int m = 0; m < H; ++m) z[m] = cx<T>{a[2 * m], a[2 * m + 1]};
+  dft<T, H>(z);
+#pragma unroll
+  for (int k = 0; k <= H; ++k) {
+    cx<T> zk = z[k % H], zc = conj(z[(H - k) % H]);
+    cx<T> e = scale(zk + zc, T(0.5));
+    cx<T> o = scale(mul_mi(zk - zc), T(0.5));
+    V[k] = e + w_const<T, R>(k) * o;
+  }
+  V[0].im = T(0);
+  V[H].im = T(0);
+}
+
+// Unnormalised inverse of rdft: a[y] = sum over the Hermitian extension of V of
+// V_k W_R^(-y k), i.e. V0 + (-1)^y V_{R/2} + 2 Re sum_{k=1}^{R/2-1} V_k W_R^(-y k).
+// Only the real parts of V[0] and V[R/2] are used.
+template <typename T, int R>
+__host__ __device__ __forceinline__ void irdft(const cx<T>* V, T* a) {
+  constexpr int H = R / 2;
+  cx<T> Z[H];
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    cx<T> vk = V[k], vc = conj(V[H - k]);
+    if (k == 0) {
+      vk = cx<T>{V[0].re, T(0)};
+      vc = cx<T>{V[H].re, T(0)};
+    }
+    cx<T> e = vk + vc;
+    cx<T> o = (vk - vc) * conj(w_const<T, R>(k));
+    Z[k] = e + mul_pi(o);
+  }
+  // unnormalised inverse DFT of length H by the swap trick
+#pragma unroll
+  for (int k = 0; k < H; ++k) Z[k] = swapri(Z[k]);
+  dft<T, H>(Z);
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    cx<T> z = swapri(Z[m]);
+    a[2 * m] = z.re;
+    a[2 * m + 1] = z.im;
+  }
+}
+
+// ------------------------------------------------------------ Stockham passes
+// Twiddles W_M^(j m), m = 0..RAD-1, from the table; three table loads per radix-8
+// butterfly (W^j, W^2j, W^4j), the rest by products of at most two levels.
+template <typename T, int RAD>
+__device__ __forceinline__ void load_twiddles(cx<T>* w, int j, int M, const V2<T>* __restrict__ tab) {
+  const int s = kTwiddleN / M;
+  w[0] = cx<T>{T(1), T(0)};
+  if constexpr (RAD >= 2) w[1] = from2<T>(tab[j * s]);
+  if constexpr (RAD >= 4) {
+    w[2] = from2<T>(tab[2 * j * s]);
+    w[3] = w[1] * w[2];
+  }
+  if constexpr (RAD >= 8) {
+    w[4] = from2<T>(tab[4 * j * s]);
+    w[5] = w[4] * w[1];
+    w[6] = w[4] * w[2];
+    w[7] = w[4] * w[3];
+  }
+  if constexpr (RAD >= 16) {
+    w[8] = from2<T>(tab[8 * j * s]);
+#pragma unroll
+    for (int m = 9; m < 16; ++m) w[m] = w[8] * w[m - 8];
+  }
+}
+
+// All passes of a length-NFFT transform for NB sequences held in registers,
+// v[s][i] = element (t + TF i) of sequence s.  LDS element e of sequence s lives
+// at lds[s * seq_stride + e * elem_stride].  Every thread of the block must call
+// this (it synchronises the block between passes).
+template <typename T, int NFFT, int P, int NS, int NB>
+__device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, V2<T>* lds, int seq_stride,
+                                           int elem_stride, const V2<T>* __restrict__ tab) {
+  if constexpr (NS < NFFT) {
+    constexpr int RAD = (P < NFFT / NS) ? P : NFFT / NS;
+    constexpr int Q = P / RAD;
+    constexpr int TF = NFFT / P;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int b = t + TF * q;
+      cx<T> w[RAD];
+      if constexpr (NS > 1) load_twiddles<T, RAD>(w, b % NS, NS * RAD, tab);
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {
+        cx<T> a[RAD];
+#pragma unroll
+        for (int m = 0; m < RAD; ++m) a[m] = v[s][q + m * Q];
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int m = 1; m < RAD; ++m) a[m] = a[m] * w[m];
+        }
+        dft<T, RAD>(a);
+#pragma unroll
+        for (int m = 0; m < RAD; ++m) v[s][q + m * Q] = a[m];
+      }
+    }
+    if constexpr (NS * RAD < NFFT) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int b = t + TF * q;
+        const int o = (b / NS) * NS * RAD + (b % NS);
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+#pragma unroll
+          for (int m = 0; m < RAD; ++m) lds[s * seq_stride + (o + m * NS) * elem_stride] = to2<T>(v[s][q + m * Q]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) v[s][i] = from2<T>(lds[s * seq_stride + (t + TF * i) * elem_stride]);
+      }
+      __syncthreads();
+      fft_passes<T, NFFT, P, NS * RAD, NB>(v, t, lds, seq_stride, elem_stride, tab);
+    }
+  }
+}
+
+template <typename T, int NFFT, int P, int NB>
+__device__ __forceinline__ void fft_forward(cx<T> (&v)[NB][P], int t, V2<T>* lds, int seq_stride, int elem_stride,
+                                            const V2<T>* __restrict__ tab) {
+  fft_passes<T, NFFT, P, 1, NB>(v, t, lds, seq_stride, elem_stride, tab);
+}
+
+template <typename T, int NFFT, int P, int NB>
+__device__ __forceinline__ void fft_inverse(cx<T> (&v)[NB][P], int t, V2<T>* lds, int seq_stride, int elem_stride,
+                                            const V2<T>* __restrict__ tab) {
+#pragma unroll
+  for (int s = 0; s < NB; ++s)
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[s][i] = swapri(v[s][i]);
+  fft_passes<T, NFFT, P, 1, NB>(v, t, lds, seq_stride, elem_stride, tab);
+#pragma unroll
+  for (int s = 0; s < NB; ++s)
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[s][i] = swapri(v[s][i]);
+}
+
+// Global memory access as uniform base + 32-bit unsigned byte offset, so the
+// compiler can use the scalar-base addressing form and keep one 32-bit offset
+// per element instead of a 64-bit address.
+template <typename V>
+__device__ __forceinline__ V ld_off(const V* base, uint32_t byte_off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename V>
+__device__ __forceinline__ void st_off(V* base, uint32_t byte_off, V v) {
+  *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// Table entry W_M^k (forward) for M dividing 4096 and 0 <= k < M.
+template <typename T>
+__device__ __forceinline__ cx<T> twiddle(const V2<T>* __restrict__ tab, int k, int M) {
+  return from2<T>(tab[k * (kTwiddleN / M)]);
+}
+
+}  // namespace fftenkf

@@ -1,0 +1,155 @@
+// Sweep 1: forward x transform plus the radix-R stage of the y transform.
+//
+// One tile = one field f (member or data) and one y1 < L: the R rows
+// y1 + L*y2.  Each thread owns the x positions {t + TF*i}: it loads the R rows
+// there (coalesced across threads), does the real R-point DFT over y2 in
+// registers, and obtains R/2 complex sequences along x:
+//   S_0 = V_0 + i V_{R/2}   (both real sequences),   S_j = V_j  (0 < j < R/2).
+// Their length-nx FFTs give every output: for 0 < j < R/2,
+//   A[j](kx)   = W_ny^(y1 j)     * S_j^(kx)            (0 <= kx <= nx/2)
+//   A[R-j](kx) = W_ny^(y1 (R-j)) * conj(S_j^(nx - kx))  (V_{R-j} = conj(V_j))
+// and S_0^ is split into V_0^ and V_{R/2}^ by Hermitian symmetry.
+#pragma once
+
+#include "fft_core.hpp"
+#include "kernels.hpp"
+
+namespace fftenkf {
+
+template <typename T, int NX>
+struct K1Geom {
+  static constexpr int P = NX < 8 ? NX : 8;
+  static constexpr int TF = NX / P;
+  static constexpr int G = TF >= 64 ? 1 : 64 / TF;  // tiles per block
+  static constexpr int threads = TF * G;
+};
+
+template <typename T, int NX, int R, int SB>
+__global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
+    const T* __restrict__ members, const T* __restrict__ data, int N, int ny, int L,
+    V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq, const V2<T>* __restrict__ tab) {
+  using Geo = K1Geom<T, NX>;
+  constexpr int P = Geo::P, TF = Geo::TF, G = Geo::G;
+  constexpr int H = R / 2;
+  constexpr int NXH = NX / 2;
+  __shared__ V2<T> lds[G * SB * NX];
+
+  const int tid = threadIdx.x;
+  const int g = tid / TF;
+  const int t = tid - g * TF;
+  const int tile = blockIdx.x * G + g;
+  const bool active = tile < (N + 1) * L;
+  const int f = active ? tile / L : 0;
+  const int y1 = active ? tile - f * L : 0;
+  const T* __restrict__ src = (f < N) ? members + (size_t)f * ny * NX : data;
+  V2<T>* my = lds + g * SB * NX;
+
+  // 1. the R rows at this thread's x positions
+  T a[R][P];
+#pragma unroll
+  for (int y2 = 0; y2 < R; ++y2) {
+    const T* __restrict__ row = src + (size_t)(y1 + L * y2) * NX + t;
+#pragma unroll
+    for (int i = 0; i < P; ++i) a[y2][i] = active ? row[TF * i] : T(0);
+  }
+
+  // 2. real R-point DFT over y2, packed into R/2 complex sequences
+  cx<T> s[H][P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    T col[R];
+#pragma unroll
+    for (int y2 = 0; y2 < R; ++y2) col[y2] = a[y2][i];
+    cx<T> V[H + 1];
+    rdft<T, R>(col, V);
+    s[0][i] = cx<T>{V[0].re, V[H].re};
+#pragma unroll
+    for (int j = 1; j < H; ++j) s[j][i] = V[j];
+  }
+
+  // 3. length-NX FFT of each sequence, SB sequences per LDS round
+#pragma unroll
+  for (int s0 = 0; s0 < H; s0 += SB) {
+    cx<T> blk[SB][P];
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int i = 0; i < P; ++i) blk[b][i] = s[s0 + b][i];
+    fft_forward<T, NX, P, SB>(blk, t, my, NX, 1, tab);
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int i = 0; i < P; ++i) s[s0 + b][i] = blk[b][i];
+  }
+
+  const size_t frow = (size_t)f * R;
+  V2<T>* __restrict__ nyq = ws_nyq + ((size_t)f * L + y1) * R;
+
+  // 4. sequences 0 < j < R/2 give rows j and R - j directly
+#pragma unroll
+  for (int j = 1; j < H; ++j) {
+    const cx<T> wj = twiddle<T>(tab, y1 * j, ny);
+    const cx<T> wc = twiddle<T>(tab, y1 * (R - j), ny);
+    V2<T>* __restrict__ rowj = ws_main + ((frow + j) * L + y1) * NXH;
+    V2<T>* __restrict__ rowc = ws_main + ((frow + (R - j)) * L + y1) * NXH;
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int m = t + TF * i;
+        const cx<T> val = s[j][i];
+        if (i < P / 2) {
+          rowj[m] = to2<T>(wj * val);
+          if (m == 0) rowc[0] = to2<T>(wc * conj(val));
+        } else if (m == NXH) {
+          nyq[j] = to2<T>(wj * val);
+          nyq[R - j] = to2<T>(wc * conj(val));
+        } else {
+          rowc[NX - m] = to2<T>(wc * conj(val));
+        }
+      }
+    }
+  }
+
+  // 5. sequence 0: V_0^(m) = (S(m) + conj S(-m)) / 2, V_{R/2}^(m) = (S(m) - conj S(-m)) / 2i
+#pragma unroll
+  for (int i = 0; i < P; ++i) my[t + TF * i] = to2<T>(s[0][i]);
+  __syncthreads();
+  if (active) {
+    const cx<T> wh = twiddle<T>(tab, y1 * H, ny);
+    V2<T>* __restrict__ row0 = ws_main + ((frow + 0) * L + y1) * NXH;
+    V2<T>* __restrict__ rowh = ws_main + ((frow + H) * L + y1) * NXH;
+#pragma unroll
+    for (int i = 0; i <= P / 2; ++i) {
+      // i < P/2 covers m in [0, NX/2); thread 0 also takes m = NX/2
+      if (i == P / 2 && t != 0) continue;
+      const int m = (i == P / 2) ? NXH : t + TF * i;
+      const cx<T> z = from2<T>(my[m]);
+      const cx<T> zc = conj(from2<T>(my[(NX - m) & (NX - 1)]));
+      const cx<T> v0 = scale(z + zc, T(0.5));
+      const cx<T> vh = wh * scale(mul_mi(z - zc), T(0.5));
+      if (m < NXH) {
+        row0[m] = to2<T>(v0);
+        rowh[m] = to2<T>(vh);
+      } else {
+        nyq[0] = to2<T>(v0);
+        nyq[H] = to2<T>(vh);
+      }
+    }
+  }
+}
+
+template <typename T, int NX, int R>
+hipError_t launch_k1_shape(const K1Args& a, hipStream_t st) {
+  using Geo = K1Geom<T, NX>;
+  constexpr int H = R / 2;
+  constexpr int budget = 65536 / (Geo::G * NX * (int)sizeof(V2<T>));
+  constexpr int SB = budget >= H ? H : budget >= 4 ? 4 : budget >= 2 ? 2 : 1;
+  const int tiles = (a.N + 1) * a.L;
+  const dim3 grid((tiles + Geo::G - 1) / Geo::G), block(Geo::threads);
+  hipLaunchKernelGGL((k1_forward<T, NX, R, SB>), grid, block, 0, st, static_cast<const T*>(a.members),
+                     static_cast<const T*>(a.data), a.N, a.ny, a.L, static_cast<V2<T>*>(a.ws_main),
+                     static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab));
+  return hipGetLastError();
+}
+
+}  // namespace fftenkf

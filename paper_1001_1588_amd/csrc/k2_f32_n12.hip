@@ -1,0 +1,19 @@
+#include "k2_spectral.hpp"
+namespace fftenkf {
+hipError_t launch_k2_f32_n12(const K2Args& a, hipStream_t s) {
+  switch (a.L) {
+    case 1: return launch_k2_shape<float, 1, 12>(a, s);
+    case 2: return launch_k2_shape<float, 2, 12>(a, s);
+    case 4: return launch_k2_shape<float, 4, 12>(a, s);
+    case 8: return launch_k2_shape<float, 8, 12>(a, s);
+    case 16: return launch_k2_shape<float, 16, 12>(a, s);
+    case 32: return launch_k2_shape<float, 32, 12>(a, s);
+    case 64: return launch_k2_shape<float, 64, 12>(a, s);
+    case 128: return launch_k2_shape<float, 128, 12>(a, s);
+    case 256: return launch_k2_shape<float, 256, 12>(a, s);
+    case 512: return launch_k2_shape<float, 512, 12>(a, s);
+
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace fftenkf

@@ -1,0 +1,19 @@
+#include "k2_spectral.hpp"
+namespace fftenkf {
+hipError_t launch_k2_f32_n8(const K2Args& a, hipStream_t s) {
+  switch (a.L) {
+    case 1: return launch_k2_shape<float, 1, 8>(a, s);
+    case 2: return launch_k2_shape<float, 2, 8>(a, s);
+    case 4: return launch_k2_shape<float, 4, 8>(a, s);
+    case 8: return launch_k2_shape<float, 8, 8>(a, s);
+    case 16: return launch_k2_shape<float, 16, 8>(a, s);
+    case 32: return launch_k2_shape<float, 32, 8>(a, s);
+    case 64: return launch_k2_shape<float, 64, 8>(a, s);
+    case 128: return launch_k2_shape<float, 128, 8>(a, s);
+    case 256: return launch_k2_shape<float, 256, 8>(a, s);
+    case 512: return launch_k2_shape<float, 512, 8>(a, s);
+
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace fftenkf

@@ -1,0 +1,241 @@
+// Sweep 2: per frequency, the rest of the y transform, eq. (2), the gain and
+// update of eq. (3) with the perturbations, and the inverse of that transform.
+//
+// A block owns a unit of C frequency columns (kx, k2) x all L values of y1, for
+// every field.  Thread (c, t2) holds, for column c, the elements y1 = t2 + TF2*i
+// of each field; after the forward length-L transform it holds the bins
+// k1 = t2 + TF2*i, i.e. ky = k2 + R*k1, of every member and of d, all in
+// registers.  Statistics, gain, perturbation and update are then local to the
+// thread; the inverse transform starts from exactly those bins and ends on the
+// y1 positions the thread loaded, which it overwrites in place.
+//
+// Main units cover kx < nx/2 ([NF][R][L][nx/2]: C adjacent kx); the Nyquist
+// column kx = nx/2 ([NF][L][R]) is covered by extra units over C adjacent k2.
+#pragma once
+
+#include <float.h>
+
+#include "fft_core.hpp"
+#include "kernels.hpp"
+#include "philox.hpp"
+
+namespace fftenkf {
+
+template <typename T> __device__ __forceinline__ T tiny_normal();
+template <> __device__ __forceinline__ float tiny_normal<float>() { return FLT_MIN; }
+template <> __device__ __forceinline__ double tiny_normal<double>() { return DBL_MIN; }
+
+template <typename T> __device__ __forceinline__ T sqrt_t(T x);
+template <> __device__ __forceinline__ float sqrt_t<float>(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return sqrt(x); }
+
+template <typename T>
+struct K2Geom {
+  static constexpr int FB = sizeof(T) == 4 ? 4 : 2;  // fields per LDS round
+};
+
+template <typename T, int L, int NMAX>
+__global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args a) {
+  constexpr int P = k2_points(L);
+  constexpr int TF2 = L / P;
+  constexpr int FB = K2Geom<T>::FB;
+  constexpr int LDSN = k2_threads_target * P;  // >= L * C
+  static_assert(NMAX % FB == 0 && NMAX % 2 == 0, "member bucket must be a multiple of the LDS batch");
+  __shared__ V2<T> lds[FB * LDSN];
+
+  const V2<T>* __restrict__ tab = static_cast<const V2<T>*>(a.tab);
+  const int C = a.C;
+  const int tid = threadIdx.x;
+  const int c = tid & (C - 1);
+  const int t2 = tid / C;
+  const int unit = blockIdx.x;
+  const int N = a.N, R = a.R, ny = a.ny;
+  const int nxh = a.nx >> 1, nh = nxh + 1;
+
+  // unit geometry: a uniform base pointer, a uniform field stride and per-thread
+  // 32-bit byte offsets of the P elements (invalid Nyquist columns read column 0
+  // and never write)
+  int k2, kx;
+  bool valid;
+  V2<T>* ubase;
+  uint32_t fstride;  // elements between fields
+  uint32_t sy;       // elements between consecutive y1
+  int cc;
+  if (unit < a.units_main) {
+    const int nchunk = nxh / C;
+    k2 = unit / nchunk;
+    const int kxc = unit - k2 * nchunk;
+    kx = kxc * C + c;
+    valid = true;
+    ubase = static_cast<V2<T>*>(a.ws_main) + (size_t)k2 * L * nxh + (size_t)kxc * C;
+    fstride = (uint32_t)ny * (uint32_t)nxh;
+    sy = (uint32_t)nxh;
+    cc = c;
+  } else {
+    const int v = unit - a.units_main;
+    k2 = v * C + c;
+    kx = nxh;
+    valid = k2 < R;
+    ubase = static_cast<V2<T>*>(a.ws_nyq) + (size_t)v * C;
+    fstride = (uint32_t)ny;
+    sy = (uint32_t)R;
+    cc = valid ? c : 0;
+  }
+  uint32_t voff[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) voff[i] = ((uint32_t)(t2 + TF2 * i) * sy + (uint32_t)cc) * (uint32_t)sizeof(V2<T>);
+  V2<T>* ldsc = lds + c;
+  const int seq = L * C;
+
+  // load: members into u, data into dv (first-pass layout)
+  cx<T> u[NMAX][P];
+  cx<T> dv[1][P];
+  static_for<0, NMAX>([&](auto F) {
+    constexpr int f = decltype(F)::value;
+    if (f < N) {
+      const V2<T>* fb = ubase + (size_t)f * fstride;
+#pragma unroll
+      for (int i = 0; i < P; ++i) u[f][i] = from2<T>(ld_off(fb, voff[i]));
+    } else {
+#pragma unroll
+      for (int i = 0; i < P; ++i) u[f][i] = cx<T>{T(0), T(0)};
+    }
+  });
+  {
+    const V2<T>* fb = ubase + (size_t)N * fstride;
+#pragma unroll
+    for (int i = 0; i < P; ++i) dv[0][i] = from2<T>(ld_off(fb, voff[i]));
+  }
+
+  // forward length-L transforms
+#pragma unroll
+  for (int f0 = 0; f0 < NMAX; f0 += FB) {
+    if (f0 < N) {
+      cx<T> blk[FB][P];
+#pragma unroll
+      for (int b = 0; b < FB; ++b)
+#pragma unroll
+        for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
+      fft_forward<T, L, P, FB>(blk, t2, ldsc, seq, C, tab);
+#pragma unroll
+      for (int b = 0; b < FB; ++b)
+#pragma unroll
+        for (int i = 0; i < P; ++i) u[f0 + b][i] = blk[b][i];
+    }
+  }
+  fft_forward<T, L, P, 1>(dv, t2, ldsc, seq, C, tab);
+
+  // eq. (2) per bin, then the gain of eq. (3)
+  const T n_tot = T(a.nx) * T(ny);
+  const T invN = T(1) / T(N);
+  const T var_scale = T(1) / (T(N - 1) * n_tot);  // unitary (eigenvalue) scale
+  const T* __restrict__ Rspec = static_cast<const T*>(a.R_spec);
+  T gain[P], amp[P];
+  int ky[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    ky[i] = k2 + R * (t2 + TF2 * i);
+    cx<T> mean{T(0), T(0)};
+#pragma unroll
+    for (int f = 0; f < NMAX; ++f)
+      if (f < N) mean = mean + u[f][i];
+    mean = scale(mean, invN);
+    T var = T(0);
+#pragma unroll
+    for (int f = 0; f < NMAX; ++f)
+      if (f < N) {
+        const cx<T> d = u[f][i] - mean;
+        var += d.re * d.re + d.im * d.im;
+      }
+    const T chat = var * var_scale;
+    T rb = T(a.r_scalar);
+    if (Rspec != nullptr && valid) rb = Rspec[(size_t)ky[i] * nh + kx];
+    const T den = chat + rb;
+    gain[i] = den < tiny_normal<T>() ? T(0) : chat / den;
+    amp[i] = sqrt_t<T>(n_tot * rb);
+    if (a.mode == K2_DEBUG_SPECTRA && valid) {
+      const size_t bin = (size_t)ky[i] * nh + kx;
+      static_cast<T*>(a.dbg_chat)[bin] = chat;
+      static_cast<T*>(a.dbg_gain)[bin] = gain[i];
+      if (a.dbg_spec != nullptr) {
+        V2<T>* sp = static_cast<V2<T>*>(a.dbg_spec);
+        const T us = T(1) / sqrt_t<T>(n_tot);
+        const size_t plane = (size_t)ny * nh;
+#pragma unroll
+        for (int f = 0; f < NMAX; ++f)
+          if (f < N) sp[f * plane + bin] = to2<T>(scale(u[f][i], us));
+        sp[N * plane + bin] = to2<T>(scale(dv[0][i], us));
+      }
+    }
+  }
+  if (a.mode == K2_DEBUG_SPECTRA) return;  // no barrier follows
+
+  // perturbations and update, two members per Philox call
+  const bool edge = (kx == 0) || (kx == nxh);
+  static_for<0, P>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const bool mirrored = edge && ky[i] > (ny >> 1);
+    const bool selfconj = edge && (ky[i] == 0 || ky[i] == (ny >> 1));
+    const int gy = mirrored ? ny - ky[i] : ky[i];
+    const uint32_t ctr0 = (uint32_t)(gy * nh + kx);
+    const T zs = selfconj ? T(1) : T(0.70710678118654752440);
+    const T zi = selfconj ? T(0) : (mirrored ? -zs : zs);
+    static_for<0, NMAX / 2>([&](auto PP) {
+      constexpr int p = decltype(PP)::value;
+      if (2 * p < N) {
+        const u32x4 w = philox4x32_10(u32x4{ctr0, (uint32_t)p, 0u, 0u}, a.key0, a.key1);
+        T za, zb;
+        box_muller<T>(w.x0, w.x1, za, zb);
+        const cx<T> e0{amp[i] * zs * za, amp[i] * zi * zb};
+        box_muller<T>(w.x2, w.x3, za, zb);
+        const cx<T> e1{amp[i] * zs * za, amp[i] * zi * zb};
+        if (a.mode == K2_DEBUG_PERTURB) {
+          if (valid) {
+            V2<T>* ep = static_cast<V2<T>*>(a.dbg_e);
+            const T us = T(1) / sqrt_t<T>(n_tot);
+            const size_t bin = (size_t)ky[i] * nh + kx, plane = (size_t)ny * nh;
+            ep[(2 * p) * plane + bin] = to2<T>(scale(e0, us));
+            if (2 * p + 1 < N) ep[(2 * p + 1) * plane + bin] = to2<T>(scale(e1, us));
+          }
+        } else {
+          const cx<T> ua = u[2 * p][i], ub = u[2 * p + 1][i];
+          u[2 * p][i] = ua + scale(dv[0][i] + e0 - ua, gain[i]);
+          if (2 * p + 1 < N) u[2 * p + 1][i] = ub + scale(dv[0][i] + e1 - ub, gain[i]);
+        }
+      }
+    });
+  });
+  if (a.mode == K2_DEBUG_PERTURB) return;  // no barrier follows
+
+  // inverse length-L transforms, written back in place
+#pragma unroll
+  for (int f0 = 0; f0 < NMAX; f0 += FB) {
+    if (f0 < N) {
+      cx<T> blk[FB][P];
+#pragma unroll
+      for (int b = 0; b < FB; ++b)
+#pragma unroll
+        for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
+      fft_inverse<T, L, P, FB>(blk, t2, ldsc, seq, C, tab);
+      if (valid) {
+#pragma unroll
+        for (int b = 0; b < FB; ++b)
+          if (f0 + b < N) {
+            V2<T>* fb = ubase + (size_t)(f0 + b) * fstride;
+#pragma unroll
+            for (int i = 0; i < P; ++i) st_off(fb, voff[i], to2<T>(blk[b][i]));
+          }
+      }
+    }
+  }
+}
+
+template <typename T, int L, int NMAX>
+hipError_t launch_k2_shape(const K2Args& a, hipStream_t st) {
+  constexpr int P = k2_points(L);
+  const dim3 grid(a.units_total), block(a.C * (L / P));
+  hipLaunchKernelGGL((k2_spectral<T, L, NMAX>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace fftenkf

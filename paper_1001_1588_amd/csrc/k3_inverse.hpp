@@ -1,0 +1,151 @@
+// Sweep 3: inverse radix-R stage of the y transform plus the inverse real x
+// transform, the mirror image of sweep 1.
+//
+// For a tile (member f, y1) let U(k2, kx) = W_ny^(-y1 k2) B(k2, kx) / (nx ny),
+// B the output of sweep 2.  The analysis member is the real part of the inverse
+// 2D DFT of the Hermitian extension of the half spectrum (a c2r transform: the
+// imaginary parts of the kx = 0 and kx = nx/2 entries are dropped).  Row
+// y1 + L*y2 of it is
+//   Re w_0(x) + (-1)^y2 Im w_0(x) + 2 Re sum_{0<j<R/2} W_R^(-y2 j) w_j(x),
+// the unnormalised inverse real R-point DFT over j of (Re w_0, w_1, ..,
+// w_{R/2-1}, Im w_0), where w_j is the inverse length-nx FFT of
+//   Z_j(m) = U(j, m)                           0 < m < nx/2
+//          = conj U(R-j, nx-m)                 nx/2 < m < nx
+//          = (U(j, m) + conj U(R-j, m)) / 2    m in {0, nx/2}
+// and w_0 that of H_0 + i H_{R/2}, H_j the Hermitian part of U(j, .).
+#pragma once
+
+#include "fft_core.hpp"
+#include "k1_forward.hpp"
+#include "kernels.hpp"
+
+namespace fftenkf {
+
+template <typename T, int NX, int R, int SB>
+__global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
+    const V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ ws_nyq, int N, int ny, int L, T out_scale,
+    T* __restrict__ out, const V2<T>* __restrict__ tab) {
+  using Geo = K1Geom<T, NX>;
+  constexpr int P = Geo::P, TF = Geo::TF, G = Geo::G;
+  constexpr int H = R / 2;
+  constexpr int NXH = NX / 2;
+  __shared__ V2<T> lds[G * SB * NX];
+
+  const int tid = threadIdx.x;
+  const int g = tid / TF;
+  const int t = tid - g * TF;
+  const int tile = blockIdx.x * G + g;
+  const bool active = tile < N * L;
+  const int f = active ? tile / L : 0;
+  const int y1 = active ? tile - f * L : 0;
+  V2<T>* my = lds + g * SB * NX;
+  const size_t frow = (size_t)f * R;
+  const V2<T>* __restrict__ nyq = ws_nyq + ((size_t)f * L + y1) * R;
+
+  // twiddle (inverse) and normalisation for row k2
+  auto tw = [&](int k2) -> cx<T> { return scale(conj(twiddle<T>(tab, y1 * k2, ny)), out_scale); };
+  auto row = [&](int k2) -> const V2<T>* { return ws_main + ((frow + k2) * L + y1) * NXH; };
+  const cx<T> zero{T(0), T(0)};
+
+  cx<T> s[H][P];
+#pragma unroll
+  for (int j = 1; j < H; ++j) {
+    const cx<T> wj = tw(j), wc = tw(R - j);
+    const V2<T>* __restrict__ rj = row(j);
+    const V2<T>* __restrict__ rc = row(R - j);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int m = t + TF * i;
+      cx<T> z = zero;
+      if (active) {
+        if (i < P / 2) {
+          if (m == 0)
+            z = scale(wj * from2<T>(rj[0]) + conj(wc * from2<T>(rc[0])), T(0.5));
+          else
+            z = wj * from2<T>(rj[m]);
+        } else if (m == NXH) {
+          z = scale(wj * from2<T>(nyq[j]) + conj(wc * from2<T>(nyq[R - j])), T(0.5));
+        } else {
+          z = conj(wc * from2<T>(rc[NX - m]));
+        }
+      }
+      s[j][i] = z;
+    }
+  }
+  {
+    const cx<T> w0 = tw(0), wh = tw(H);
+    const V2<T>* __restrict__ r0 = row(0);
+    const V2<T>* __restrict__ rh = row(H);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int m = t + TF * i;
+      cx<T> h0 = zero, hh = zero;
+      if (active) {
+        if (i < P / 2) {
+          h0 = w0 * from2<T>(r0[m]);
+          hh = wh * from2<T>(rh[m]);
+          if (m == 0) {
+            h0.im = T(0);
+            hh.im = T(0);
+          }
+        } else if (m == NXH) {
+          h0 = cx<T>{(w0 * from2<T>(nyq[0])).re, T(0)};
+          hh = cx<T>{(wh * from2<T>(nyq[H])).re, T(0)};
+        } else {
+          h0 = conj(w0 * from2<T>(r0[NX - m]));
+          hh = conj(wh * from2<T>(rh[NX - m]));
+        }
+      }
+      s[0][i] = h0 + mul_pi(hh);
+    }
+  }
+
+  // inverse length-NX FFTs
+#pragma unroll
+  for (int s0 = 0; s0 < H; s0 += SB) {
+    cx<T> blk[SB][P];
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int i = 0; i < P; ++i) blk[b][i] = s[s0 + b][i];
+    fft_inverse<T, NX, P, SB>(blk, t, my, NX, 1, tab);
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int i = 0; i < P; ++i) s[s0 + b][i] = blk[b][i];
+  }
+
+  // inverse real R-point DFT over j, then the R output rows
+  if (active) {
+    T* __restrict__ dst = out + (size_t)f * ny * NX + t;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      cx<T> V[H + 1];
+      V[0] = cx<T>{s[0][i].re, T(0)};
+      V[H] = cx<T>{s[0][i].im, T(0)};
+#pragma unroll
+      for (int j = 1; j < H; ++j) V[j] = s[j][i];
+      T col[R];
+      irdft<T, R>(V, col);
+#pragma unroll
+      for (int y2 = 0; y2 < R; ++y2) dst[(size_t)(y1 + L * y2) * NX + TF * i] = col[y2];
+    }
+  }
+}
+
+template <typename T, int NX, int R>
+hipError_t launch_k3_shape(const K3Args& a, hipStream_t st) {
+  using Geo = K1Geom<T, NX>;
+  constexpr int H = R / 2;
+  constexpr int budget = 65536 / (Geo::G * NX * (int)sizeof(V2<T>));
+  constexpr int SB = budget >= H ? H : budget >= 4 ? 4 : budget >= 2 ? 2 : 1;
+  const int tiles = a.N * a.L;
+  const dim3 grid((tiles + Geo::G - 1) / Geo::G), block(Geo::threads);
+  const T out_scale = T(1) / (T(a.nx) * T(a.ny));
+  hipLaunchKernelGGL((k3_inverse<T, NX, R, SB>), grid, block, 0, st, static_cast<const V2<T>*>(a.ws_main),
+                     static_cast<const V2<T>*>(a.ws_nyq), a.N, a.ny, a.L, out_scale, static_cast<T*>(a.out),
+                     static_cast<const V2<T>*>(a.tab));
+  return hipGetLastError();
+}
+
+}  // namespace fftenkf

@@ -1,0 +1,81 @@
+// Internal launch interface of the three sweeps of one analysis.
+//
+// Grid factorisation: ny = R * L.  A row index is y = y1 + L * y2 and a
+// frequency ky = k2 + R * k1 (y1, k1 < L; y2, k2 < R).  Then
+//   X[k2 + R k1] = sum_y1 W_L^(y1 k1) * [ W_ny^(y1 k2) * sum_y2 W_R^(y2 k2) x[y1 + L y2] ],
+// so the first sweep (k1) does the x transform of R rows y1 + L*y2 plus the
+// radix-R stage over y2 and the W_ny^(y1 k2) twiddle; the second sweep (k2) does
+// the remaining length-L transform over y1 for each (k2, kx), the statistics,
+// the gain, the perturbations and the update, then the inverse length-L
+// transform; the third sweep (k3) undoes the first.
+//
+// Workspace (complex, dtype T):
+//   main [NF][R][L][nx/2]   element (f, k2, y1, kx) for kx < nx/2
+//   nyq  [NF][L][R]         element (f, y1, k2) for kx = nx/2 (the Nyquist column)
+// with NF = N + 1 fields (the N members, then the data d).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fftenkf {
+
+struct K1Args {
+  const void* members;  // [N][ny][nx]
+  const void* data;     // [ny][nx]
+  int N, ny, nx, R, L;
+  void* ws_main;
+  void* ws_nyq;
+  const void* tab;  // W_4096^k table of dtype's complex type (device)
+};
+
+enum K2Mode { K2_ANALYZE = 0, K2_DEBUG_SPECTRA = 1, K2_DEBUG_PERTURB = 2 };
+
+struct K2Args {
+  void* ws_main;
+  void* ws_nyq;
+  const void* R_spec;  // [ny][nx/2+1] or nullptr
+  double r_scalar;
+  int N, ny, nx, R, L, C, units_main, units_total;
+  uint32_t key0, key1;
+  int mode;
+  void* dbg_chat;  // [ny][nx/2+1] real
+  void* dbg_gain;  // [ny][nx/2+1] real
+  void* dbg_spec;  // [N+1][ny][nx/2+1] complex, or nullptr
+  void* dbg_e;     // [N][ny][nx/2+1] complex
+  const void* tab;
+};
+
+struct K3Args {
+  const void* ws_main;
+  const void* ws_nyq;
+  int N, ny, nx, R, L;
+  void* out;  // [N][ny][nx]
+  const void* tab;
+};
+
+// K2 geometry chosen for a given length L (shared by host planning and kernels).
+constexpr int k2_points(int L) { return L < 4 ? L : 4; }
+constexpr int k2_threads_target = 256;
+
+// Largest member count held in registers by the fused spectral sweep.
+constexpr int kMaxMembersF32 = 24;
+constexpr int kMaxMembersF64 = 8;
+
+hipError_t launch_k1_f32(const K1Args& a, hipStream_t s);
+hipError_t launch_k1_f64(const K1Args& a, hipStream_t s);
+hipError_t launch_k2_f32(const K2Args& a, hipStream_t s);
+hipError_t launch_k2_f64(const K2Args& a, hipStream_t s);
+hipError_t launch_k3_f32(const K3Args& a, hipStream_t s);
+hipError_t launch_k3_f64(const K3Args& a, hipStream_t s);
+
+// Device address of the W_4096^k table (float2 for dtype 0, double2 for 1) on
+// the current device, filled from float64 host values on first use.
+hipError_t twiddle_table(int dtype, const void** out);
+
+// Supported member counts of the spectral sweep are grouped in buckets of
+// register arrays; returns the bucket for N, or 0 if N is too large.
+int k2_member_bucket(int dtype, int N);
+
+}  // namespace fftenkf

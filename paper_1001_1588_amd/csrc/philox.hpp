@@ -1,0 +1,63 @@
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As Easy
+// as 1, 2, 3", SC'11) and Box-Muller, for the spectral perturbations e_k ~ N(0, R).
+//
+// Round: (hi0, lo0) = M0 * x0, (hi1, lo1) = M1 * x2,
+//        x <- (hi1 ^ x1 ^ k0, lo1, hi0 ^ x3 ^ k1, lo0);
+// key bumped by the Weyl constants between rounds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fftenkf {
+
+struct u32x4 {
+  uint32_t x0, x1, x2, x3;
+};
+
+__host__ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.x2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c = u32x4{hi1 ^ c.x1 ^ k0, lo1, hi0 ^ c.x3 ^ k1, lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Uniform in (0, 1): (2 * (w >> 9) + 1) * 2^-24, exact in binary32 and binary64.
+template <typename T>
+__device__ __forceinline__ T uniform_open(uint32_t w) {
+  return T((int)(((w >> 9) << 1) | 1u)) * T(5.9604644775390625e-08);
+}
+
+// Two standard normals from two words (Box-Muller): rho (cos 2 pi u2, sin 2 pi u2).
+template <typename T> __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T& a, T& b);
+
+template <>
+__device__ __forceinline__ void box_muller<float>(uint32_t wa, uint32_t wb, float& a, float& b) {
+  const float u1 = uniform_open<float>(wa);
+  const float u2 = uniform_open<float>(wb);
+  const float rho = sqrtf(-2.0f * logf(u1));
+  float s, c;
+  sincospif(2.0f * u2, &s, &c);
+  a = rho * c;
+  b = rho * s;
+}
+
+template <>
+__device__ __forceinline__ void box_muller<double>(uint32_t wa, uint32_t wb, double& a, double& b) {
+  const double u1 = uniform_open<double>(wa);
+  const double u2 = uniform_open<double>(wb);
+  const double rho = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  a = rho * c;
+  b = rho * s;
+}
+
+}  // namespace fftenkf

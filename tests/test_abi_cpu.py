@@ -1,0 +1,108 @@
+"""The C-ABI library loads, exports what include/fftenkf.h declares, and rejects
+bad arguments before touching the GPU (these run without a device)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1001_1588_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fftenkf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(fftenkf_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("fftenkf_analyze", "fftenkf_workspace_bytes", "fftenkf_strerror", "fftenkf_last_error",
+                 "fftenkf_debug_spectra", "fftenkf_debug_perturb"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(built_lib):
+    lib = ctypes.CDLL(built_lib)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(_lib.EXPORTS) == set(declared_functions())
+
+
+def _ens(**kw):
+    d = dict(n_members=4, ny=16, nx=16, dtype=_lib.F32, members=0x100000, workspace=0x800000,
+             workspace_bytes=1 << 20, stream=None, r_scalar=0.05)
+    d.update(kw)
+    return _lib.Ens(**d)
+
+
+def call(e, data=0x200000, R=None, out=0x300000):
+    lib = _lib.lib()
+    return lib.fftenkf_analyze(ctypes.byref(e) if e is not None else None, data, R, 1, out)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dtype=2), _lib.EINVAL),
+    (dict(n_members=1), _lib.EINVAL),
+    (dict(n_members=0), _lib.EINVAL),
+    (dict(ny=12), _lib.EUNSUPPORTED),
+    (dict(nx=4), _lib.EUNSUPPORTED),
+    (dict(nx=8192), _lib.EUNSUPPORTED),
+    (dict(ny=0), _lib.EUNSUPPORTED),
+    (dict(n_members=25), _lib.EUNSUPPORTED),
+    (dict(n_members=9, dtype=_lib.F64), _lib.EUNSUPPORTED),
+    (dict(members=None), _lib.EINVAL),
+    (dict(workspace=None), _lib.EINVAL),
+    (dict(workspace_bytes=1000), _lib.EINVAL),
+    (dict(members=0x100008), _lib.EINVAL),
+    (dict(workspace=0x800010), _lib.EINVAL),
+], ids=lambda v: str(v))
+def test_validation_errors(built_lib, kw, status):
+    assert call(_ens(**kw)) == status
+    assert _lib.lib().fftenkf_last_error().decode()
+
+
+def test_null_descriptor_and_buffers(built_lib):
+    assert call(None) == _lib.EINVAL
+    assert call(_ens(), data=None) == _lib.EINVAL
+    assert call(_ens(), out=None) == _lib.EINVAL
+    assert call(_ens(), out=0x300004) == _lib.EINVAL                   # misaligned
+    assert call(_ens(r_scalar=-1.0)) == _lib.EINVAL                    # negative R without R_spec
+    assert call(_ens(r_scalar=float("nan"))) == _lib.EINVAL
+
+
+def test_partial_overlap_rejected(built_lib):
+    field = 16 * 16 * 4
+    assert call(_ens(), out=0x100000 + field) == _lib.EINVAL            # out overlaps members, not equal
+    assert call(_ens(), data=0x800000 + 256) == _lib.EINVAL              # data inside the workspace
+    assert call(_ens(), R=0x200000 + 64) == _lib.EINVAL                  # R_spec overlaps data
+    assert call(_ens(workspace=0x100000 + 256)) == _lib.EINVAL          # workspace overlaps members
+
+
+def test_workspace_formula(built_lib):
+    lib = _lib.lib()
+    for (N, ny, nx, dt, s) in [(20, 2048, 2048, 0, 4), (5, 64, 64, 1, 8), (2, 8, 8, 0, 4), (24, 4096, 4096, 0, 4)]:
+        nh = nx // 2 + 1
+        raw = (N + 1) * ny * nh * 2 * s + ny * nh * s
+        assert lib.fftenkf_workspace_bytes(N, ny, nx, dt) == (raw + 255) // 256 * 256
+    assert lib.fftenkf_workspace_bytes(1, 8, 8, 0) == 0
+    assert lib.fftenkf_workspace_bytes(4, 8, 12, 0) == 0
+    assert lib.fftenkf_workspace_bytes(4, 8, 8, 3) == 0
+    assert lib.fftenkf_max_members(0) == 24 and lib.fftenkf_max_members(1) == 8
+
+
+def test_strerror(built_lib):
+    lib = _lib.lib()
+    assert lib.fftenkf_strerror(0) == b"success"
+    assert lib.fftenkf_strerror(-2) == b"unsupported shape"
+    assert lib.fftenkf_strerror(7) == b"unknown status"
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.lib()

@@ -28,7 +28,7 @@ MUTANTS = [
     ("enkf.py", "(x[:, None] - x[None, :]) % nx]", "(x[None, :] - x[:, None]) % nx]"),
     ("dft.py", "ang = (2.0 * np.pi / m)", "ang = (-2.0 * np.pi / m)"),
     ("dft.py", "np.conj(S[..., ky, nx - kx])", "S[..., ky, nx - kx]"),
-    ("dft.py", "u @ wx.real + 1j * (u @ wx.imag)", "u @ wx.real - 1j * (u @ wx.imag)"),
+    ("dft.py", "u @ wx_re + 1j * (u @ wx_im)", "u @ wx_re - 1j * (u @ wx_im)"),
     ("dft.py", "ky = (-np.arange(ny)) % ny", "ky = np.arange(ny)"),
     ("dft.py", "(dft_matrix(ny, +1) @ full @ dft_matrix(nx, +1))", "(dft_matrix(ny, -1) @ full @ dft_matrix(nx, +1))"),
     ("philox.py", "hi1 ^ x[1] ^ k0, lo1, hi0 ^ x[3] ^ k1", "hi1 ^ x[1] ^ k1, lo1, hi0 ^ x[3] ^ k0"),
