@@ -68,6 +68,49 @@ def sweep_bytes(N: int, ny: int, nx: int, s: int, rspec_array: bool) -> dict:
     }
 
 
+def profiled_traffic(sweep: str):
+    """HBM bytes per launch of `sweep` from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain
+    copy of known size), or None if the kernel's sources changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "large2048_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))["kernels"].get(sweep)
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def copy_ceiling(mib: int, hip: HipEvents, reps: int = 10) -> dict:
+    """Device-to-device copy of `mib` MiB (read + write counted): the achievable
+    HBM rate on this machine, and the reference kernel for scaling byte counters."""
+    import torch
+
+    src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = hip.create(), hip.create()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    hip.h.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    hip.h.hipEventRecord(ctypes.c_void_p(a), stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    hip.h.hipEventRecord(ctypes.c_void_p(b), stream)
+    torch.cuda.synchronize()
+    ms = hip.elapsed_ms(a, b) / reps
+    hip.destroy(a)
+    hip.destroy(b)
+    return {"bytes_per_copy": 2 * (mib << 20), "ms": ms, "GBps": 2 * (mib << 20) / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(tw, members: int) -> dict:
     from threadpoolctl import threadpool_info
 
@@ -92,6 +135,7 @@ def main() -> int:
     ap.add_argument("--rspec", choices=["array", "scalar"], default="array")
     ap.add_argument("--cpu-members", type=int, default=20, help="members in the CPU oracle sample (0 = skip)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the device copy ceiling probe (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -162,13 +206,16 @@ def main() -> int:
                                f"R=0.05 I ({'R_spec array' if args.rspec == 'array' else 'scalar r'})",
                    "grid": [ny, nx], "members": N, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": names[dom]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(names[dom]) if args.rspec == "array" else None,
+                     "kernel": names[dom], "algorithmic_bytes": b[names[dom]]},
         "sweep_ms": {names[i]: float(avg[i]) for i in range(3)},
         "sweep_hbm_frac": {names[i]: b[names[i]] / (avg[i] * 1e-3) / 1e9 / HBM_PEAK_GBS for i in range(3)},
         "path_bytes_per_step": b["path"],
         "path_hbm_frac": b["path"] / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "gpu_event_ms_per_step": gpu_span_ms / args.steps,
     }
+    if args.copy_mib > 0:
+        result["copy_ceiling"] = copy_ceiling(args.copy_mib, hip)
     if args.cpu_members > 0:
         result["cpu_baseline"] = cpu_baseline(tw, min(args.cpu_members, N))
     print(json.dumps(result), flush=True)

@@ -234,13 +234,46 @@ __device__ __forceinline__ void load_twiddles(cx<T>* w, int j, int M, const V2<T
   }
 }
 
+// LDS index with one padding element after every 8: the strided writes of the
+// Stockham passes then spread over the banks instead of piling on a few.
+__device__ __forceinline__ int lds_pad(int idx) { return idx + (idx >> 3); }
+// Elements to allocate for n logical elements.
+__host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 3) + 1; }
+
 // All passes of a length-NFFT transform for NB sequences held in registers,
-// v[s][i] = element (t + TF i) of sequence s.  LDS element e of sequence s lives
-// at lds[s * seq_stride + e * elem_stride].  Every thread of the block must call
-// this (it synchronises the block between passes).
-template <typename T, int NFFT, int P, int NS, int NB>
-__device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, V2<T>* lds, int seq_stride,
-                                           int elem_stride, const V2<T>* __restrict__ tab) {
+// v[s][i] = element (t + TF i) of sequence s.  In LDS, sequence s occupies the
+// block [s * SEQP, (s + 1) * SEQP) and its element e sits at
+// lds_pad(e * elem_stride + lp.off) inside it (SEQP >= lds_padded_size of the
+// largest index), so the per-sequence part of every address is a constant.
+// Every thread of the block must call this (it synchronises the block).
+//
+// LDS exchange: with buf1 == nullptr each exchange writes buf0, synchronises,
+// reads, and synchronises again before the buffer can be rewritten.  With a
+// second buffer the exchanges alternate between buf0 and buf1 (`parity`, kept
+// by the caller across calls) and need one synchronisation each: a buffer is
+// rewritten only after the next exchange's synchronisation.
+struct LdsPair {
+  void* buf0;
+  void* buf1;
+  int parity;
+  int off;  // per-thread element offset added to every index (e.g. a column)
+};
+
+// Order a wave's own LDS writes before its later reads (and reads before later
+// writes) without a block-wide barrier: LDS instructions of one wave execute in
+// order, so only the compiler has to be kept from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// WAVE = true: all TF threads of a sequence belong to one wave and the LDS
+// region they exchange through is private to that wave, so exchanges need no
+// block synchronisation (buf1 is then ignored).
+template <typename T, int NFFT, int P, int NS, int NB, int SEQP, bool WAVE = false>
+__device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, LdsPair& lp, int elem_stride,
+                                           const V2<T>* __restrict__ tab) {
   if constexpr (NS < NFFT) {
     constexpr int RAD = (P < NFFT / NS) ? P : NFFT / NS;
     constexpr int Q = P / RAD;
@@ -265,42 +298,50 @@ __device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, V2<T>* lds,
       }
     }
     if constexpr (NS * RAD < NFFT) {
+      V2<T>* lds = static_cast<V2<T>*>((!WAVE && lp.buf1 != nullptr && lp.parity) ? lp.buf1 : lp.buf0);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int b = t + TF * q;
         const int o = (b / NS) * NS * RAD + (b % NS);
 #pragma unroll
-        for (int s = 0; s < NB; ++s) {
+        for (int m = 0; m < RAD; ++m) {
+          V2<T>* dst = lds + lds_pad((o + m * NS) * elem_stride + lp.off);
 #pragma unroll
-          for (int m = 0; m < RAD; ++m) lds[s * seq_stride + (o + m * NS) * elem_stride] = to2<T>(v[s][q + m * Q]);
+          for (int s = 0; s < NB; ++s) dst[s * SEQP] = to2<T>(v[s][q + m * Q]);
         }
       }
-      __syncthreads();
+      if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
 #pragma unroll
-      for (int s = 0; s < NB; ++s) {
+      for (int i = 0; i < P; ++i) {
+        const V2<T>* src = lds + lds_pad((t + TF * i) * elem_stride + lp.off);
 #pragma unroll
-        for (int i = 0; i < P; ++i) v[s][i] = from2<T>(lds[s * seq_stride + (t + TF * i) * elem_stride]);
+        for (int s = 0; s < NB; ++s) v[s][i] = from2<T>(src[s * SEQP]);
       }
-      __syncthreads();
-      fft_passes<T, NFFT, P, NS * RAD, NB>(v, t, lds, seq_stride, elem_stride, tab);
+      if constexpr (WAVE)
+        wave_lds_sync();
+      else if (lp.buf1 == nullptr)
+        __syncthreads();
+      else
+        lp.parity ^= 1;
+      fft_passes<T, NFFT, P, NS * RAD, NB, SEQP, WAVE>(v, t, lp, elem_stride, tab);
     }
   }
 }
 
-template <typename T, int NFFT, int P, int NB>
-__device__ __forceinline__ void fft_forward(cx<T> (&v)[NB][P], int t, V2<T>* lds, int seq_stride, int elem_stride,
+template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false>
+__device__ __forceinline__ void fft_forward(cx<T> (&v)[NB][P], int t, LdsPair& lp, int elem_stride,
                                             const V2<T>* __restrict__ tab) {
-  fft_passes<T, NFFT, P, 1, NB>(v, t, lds, seq_stride, elem_stride, tab);
+  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE>(v, t, lp, elem_stride, tab);
 }
 
-template <typename T, int NFFT, int P, int NB>
-__device__ __forceinline__ void fft_inverse(cx<T> (&v)[NB][P], int t, V2<T>* lds, int seq_stride, int elem_stride,
+template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false>
+__device__ __forceinline__ void fft_inverse(cx<T> (&v)[NB][P], int t, LdsPair& lp, int elem_stride,
                                             const V2<T>* __restrict__ tab) {
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll
     for (int i = 0; i < P; ++i) v[s][i] = swapri(v[s][i]);
-  fft_passes<T, NFFT, P, 1, NB>(v, t, lds, seq_stride, elem_stride, tab);
+  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE>(v, t, lp, elem_stride, tab);
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll

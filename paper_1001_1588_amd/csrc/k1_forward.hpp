@@ -32,7 +32,8 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
   constexpr int P = Geo::P, TF = Geo::TF, G = Geo::G;
   constexpr int H = R / 2;
   constexpr int NXH = NX / 2;
-  __shared__ V2<T> lds[G * SB * NX];
+  constexpr int SEQP = lds_padded_size(NX);
+  __shared__ V2<T> lds[G * SB * SEQP];
 
   const int tid = threadIdx.x;
   const int g = tid / TF;
@@ -42,7 +43,8 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
   const int f = active ? tile / L : 0;
   const int y1 = active ? tile - f * L : 0;
   const T* __restrict__ src = (f < N) ? members + (size_t)f * ny * NX : data;
-  V2<T>* my = lds + g * SB * NX;
+  V2<T>* my = lds + g * SB * SEQP;
+  LdsPair lp{my, nullptr, 0, 0};
 
   // 1. the R rows at this thread's x positions
   T a[R][P];
@@ -75,7 +77,7 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
     for (int b = 0; b < SB; ++b)
 #pragma unroll
       for (int i = 0; i < P; ++i) blk[b][i] = s[s0 + b][i];
-    fft_forward<T, NX, P, SB>(blk, t, my, NX, 1, tab);
+    fft_forward<T, NX, P, SB, SEQP>(blk, t, lp, 1, tab);
 #pragma unroll
     for (int b = 0; b < SB; ++b)
 #pragma unroll
@@ -112,7 +114,7 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
 
   // 5. sequence 0: V_0^(m) = (S(m) + conj S(-m)) / 2, V_{R/2}^(m) = (S(m) - conj S(-m)) / 2i
 #pragma unroll
-  for (int i = 0; i < P; ++i) my[t + TF * i] = to2<T>(s[0][i]);
+  for (int i = 0; i < P; ++i) my[lds_pad(t + TF * i)] = to2<T>(s[0][i]);
   __syncthreads();
   if (active) {
     const cx<T> wh = twiddle<T>(tab, y1 * H, ny);
@@ -123,8 +125,8 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
       // i < P/2 covers m in [0, NX/2); thread 0 also takes m = NX/2
       if (i == P / 2 && t != 0) continue;
       const int m = (i == P / 2) ? NXH : t + TF * i;
-      const cx<T> z = from2<T>(my[m]);
-      const cx<T> zc = conj(from2<T>(my[(NX - m) & (NX - 1)]));
+      const cx<T> z = from2<T>(my[lds_pad(m)]);
+      const cx<T> zc = conj(from2<T>(my[lds_pad((NX - m) & (NX - 1))]));
       const cx<T> v0 = scale(z + zc, T(0.5));
       const cx<T> vh = wh * scale(mul_mi(z - zc), T(0.5));
       if (m < NXH) {
@@ -142,7 +144,9 @@ template <typename T, int NX, int R>
 hipError_t launch_k1_shape(const K1Args& a, hipStream_t st) {
   using Geo = K1Geom<T, NX>;
   constexpr int H = R / 2;
-  constexpr int budget = 65536 / (Geo::G * NX * (int)sizeof(V2<T>));
+  // sequences per LDS round: keep the (padded) buffer within 80 KB so two
+  // blocks share a CU
+  constexpr int budget = 81920 / (Geo::G * lds_padded_size(NX) * (int)sizeof(V2<T>));
   constexpr int SB = budget >= H ? H : budget >= 4 ? 4 : budget >= 2 ? 2 : 1;
   const int tiles = (a.N + 1) * a.L;
   const dim3 grid((tiles + Geo::G - 1) / Geo::G), block(Geo::threads);

@@ -2,15 +2,24 @@
 // update of eq. (3) with the perturbations, and the inverse of that transform.
 //
 // A block owns a unit of C frequency columns (kx, k2) x all L values of y1, for
-// every field.  Thread (c, t2) holds, for column c, the elements y1 = t2 + TF2*i
-// of each field; after the forward length-L transform it holds the bins
-// k1 = t2 + TF2*i, i.e. ky = k2 + R*k1, of every member and of d, all in
-// registers.  Statistics, gain, perturbation and update are then local to the
-// thread; the inverse transform starts from exactly those bins and ends on the
-// y1 positions the thread loaded, which it overwrites in place.
+// every field (the N members and d), and keeps all of it in registers.  Thread
+// (c, t2) = (tid % C, tid / C) holds, for column c, the elements
+// y1 = t2 + TF2 * i (i < P) of each field: consecutive threads touch
+// consecutive kx, so loads and stores are coalesced.  After the forward
+// length-L transform it holds the bins k1 = t2 + TF2 * i, i.e. ky = k2 + R * k1,
+// of every member and of d: statistics, gain, perturbation and update are
+// thread-local.  The inverse transform starts from exactly those bins and ends
+// on the y1 positions the thread loaded, which it overwrites in place.  The
+// exchanges between passes go through two LDS buffers in turn (one block
+// synchronisation each); every field's loads are issued before any transform.
 //
 // Main units cover kx < nx/2 ([NF][R][L][nx/2]: C adjacent kx); the Nyquist
-// column kx = nx/2 ([NF][L][R]) is covered by extra units over C adjacent k2.
+// column kx = nx/2 ([NF][L][R]) is covered by extra units over C adjacent k2,
+// placed first in the grid so they do not trail.  A unit's row segments are C
+// complex values; when that is less than a 128-byte line, the two units
+// sharing each line are given to blocks b and b + 8, which the hardware sends
+// to the same XCD one after the other, so the second read of every line is an
+// L2 hit rather than a second HBM fetch.
 #pragma once
 
 #include <float.h>
@@ -32,6 +41,11 @@ template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return 
 template <typename T>
 struct K2Geom {
   static constexpr int FB = sizeof(T) == 4 ? 4 : 2;  // fields per LDS round
+  // padded LDS block of one field: L rows of at most k2_threads_target * P / L columns
+  template <int L>
+  static constexpr int seqp() { return lds_padded_size(k2_threads_target * k2_points(L)); }
+  template <int L>
+  static constexpr size_t lds_bytes() { return 2 * (size_t)FB * seqp<L>() * sizeof(V2<T>); }
 };
 
 template <typename T, int L, int NMAX>
@@ -39,9 +53,9 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   constexpr int P = k2_points(L);
   constexpr int TF2 = L / P;
   constexpr int FB = K2Geom<T>::FB;
-  constexpr int LDSN = k2_threads_target * P;  // >= L * C
+  constexpr int SEQP = K2Geom<T>::template seqp<L>();
   static_assert(NMAX % FB == 0 && NMAX % 2 == 0, "member bucket must be a multiple of the LDS batch");
-  __shared__ V2<T> lds[FB * LDSN];
+  extern __shared__ unsigned char k2_lds_raw[];  // two buffers of FB fields
 
   const V2<T>* __restrict__ tab = static_cast<const V2<T>*>(a.tab);
   const int C = a.C;
@@ -61,10 +75,16 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   uint32_t fstride;  // elements between fields
   uint32_t sy;       // elements between consecutive y1
   int cc;
-  if (unit < a.units_main) {
+  const int units_nyq = a.units_total - a.units_main;
+  if (unit >= units_nyq) {
+    int um = unit - units_nyq;
+    if (a.pair_xcd) {
+      const int x = um & 7, q = um >> 3;
+      um = 2 * (((q >> 1) << 3) + x) + (q & 1);
+    }
     const int nchunk = nxh / C;
-    k2 = unit / nchunk;
-    const int kxc = unit - k2 * nchunk;
+    k2 = um / nchunk;
+    const int kxc = um - k2 * nchunk;
     kx = kxc * C + c;
     valid = true;
     ubase = static_cast<V2<T>*>(a.ws_main) + (size_t)k2 * L * nxh + (size_t)kxc * C;
@@ -72,7 +92,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
     sy = (uint32_t)nxh;
     cc = c;
   } else {
-    const int v = unit - a.units_main;
+    const int v = unit;
     k2 = v * C + c;
     kx = nxh;
     valid = k2 < R;
@@ -84,8 +104,8 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   uint32_t voff[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) voff[i] = ((uint32_t)(t2 + TF2 * i) * sy + (uint32_t)cc) * (uint32_t)sizeof(V2<T>);
-  V2<T>* ldsc = lds + c;
-  const int seq = L * C;
+  V2<T>* lds0 = reinterpret_cast<V2<T>*>(k2_lds_raw);
+  LdsPair lp{lds0, lds0 + FB * SEQP, 0, c};
 
   // load: members into u, data into dv (first-pass layout)
   cx<T> u[NMAX][P];
@@ -116,16 +136,17 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
-      fft_forward<T, L, P, FB>(blk, t2, ldsc, seq, C, tab);
+      fft_forward<T, L, P, FB, SEQP>(blk, t2, lp, C, tab);
 #pragma unroll
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) u[f0 + b][i] = blk[b][i];
     }
   }
-  fft_forward<T, L, P, 1>(dv, t2, ldsc, seq, C, tab);
+  fft_forward<T, L, P, 1, SEQP>(dv, t2, lp, C, tab);
+  const bool valid_w = valid;
 
-  // eq. (2) per bin, then the gain of eq. (3)
+  // ---- eq. (2) per bin, then the gain of eq. (3)
   const T n_tot = T(a.nx) * T(ny);
   const T invN = T(1) / T(N);
   const T var_scale = T(1) / (T(N - 1) * n_tot);  // unitary (eigenvalue) scale
@@ -149,11 +170,11 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
       }
     const T chat = var * var_scale;
     T rb = T(a.r_scalar);
-    if (Rspec != nullptr && valid) rb = Rspec[(size_t)ky[i] * nh + kx];
+    if (Rspec != nullptr && valid_w) rb = Rspec[(size_t)ky[i] * nh + kx];
     const T den = chat + rb;
     gain[i] = den < tiny_normal<T>() ? T(0) : chat / den;
     amp[i] = sqrt_t<T>(n_tot * rb);
-    if (a.mode == K2_DEBUG_SPECTRA && valid) {
+    if (a.mode == K2_DEBUG_SPECTRA && valid_w) {
       const size_t bin = (size_t)ky[i] * nh + kx;
       static_cast<T*>(a.dbg_chat)[bin] = chat;
       static_cast<T*>(a.dbg_gain)[bin] = gain[i];
@@ -168,11 +189,11 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
       }
     }
   }
-  if (a.mode == K2_DEBUG_SPECTRA) return;  // no barrier follows
+  if (a.mode == K2_DEBUG_SPECTRA) return;  // no synchronisation follows
 
-  // perturbations and update, two members per Philox call
+  // ---- perturbations and update, two members per Philox call
   const bool edge = (kx == 0) || (kx == nxh);
-  static_for<0, P>([&](auto I) {
+  static_for<0, P>([&](auto I) __attribute__((always_inline)) {
     constexpr int i = decltype(I)::value;
     const bool mirrored = edge && ky[i] > (ny >> 1);
     const bool selfconj = edge && (ky[i] == 0 || ky[i] == (ny >> 1));
@@ -180,7 +201,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
     const uint32_t ctr0 = (uint32_t)(gy * nh + kx);
     const T zs = selfconj ? T(1) : T(0.70710678118654752440);
     const T zi = selfconj ? T(0) : (mirrored ? -zs : zs);
-    static_for<0, NMAX / 2>([&](auto PP) {
+    static_for<0, NMAX / 2>([&](auto PP) __attribute__((always_inline)) {
       constexpr int p = decltype(PP)::value;
       if (2 * p < N) {
         const u32x4 w = philox4x32_10(u32x4{ctr0, (uint32_t)p, 0u, 0u}, a.key0, a.key1);
@@ -190,7 +211,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
         box_muller<T>(w.x2, w.x3, za, zb);
         const cx<T> e1{amp[i] * zs * za, amp[i] * zi * zb};
         if (a.mode == K2_DEBUG_PERTURB) {
-          if (valid) {
+          if (valid_w) {
             V2<T>* ep = static_cast<V2<T>*>(a.dbg_e);
             const T us = T(1) / sqrt_t<T>(n_tot);
             const size_t bin = (size_t)ky[i] * nh + kx, plane = (size_t)ny * nh;
@@ -205,9 +226,9 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
       }
     });
   });
-  if (a.mode == K2_DEBUG_PERTURB) return;  // no barrier follows
+  if (a.mode == K2_DEBUG_PERTURB) return;  // no synchronisation follows
 
-  // inverse length-L transforms, written back in place
+  // ---- inverse length-L transforms, written back in place
 #pragma unroll
   for (int f0 = 0; f0 < NMAX; f0 += FB) {
     if (f0 < N) {
@@ -216,7 +237,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
-      fft_inverse<T, L, P, FB>(blk, t2, ldsc, seq, C, tab);
+      fft_inverse<T, L, P, FB, SEQP>(blk, t2, lp, C, tab);
       if (valid) {
 #pragma unroll
         for (int b = 0; b < FB; ++b)
@@ -234,7 +255,11 @@ template <typename T, int L, int NMAX>
 hipError_t launch_k2_shape(const K2Args& a, hipStream_t st) {
   constexpr int P = k2_points(L);
   const dim3 grid(a.units_total), block(a.C * (L / P));
-  hipLaunchKernelGGL((k2_spectral<T, L, NMAX>), grid, block, 0, st, a);
+  constexpr size_t lds_bytes = K2Geom<T>::template lds_bytes<L>();
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_spectral<T, L, NMAX>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((k2_spectral<T, L, NMAX>), grid, block, lds_bytes, st, a);
   return hipGetLastError();
 }
 

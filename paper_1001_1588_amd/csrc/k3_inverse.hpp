@@ -29,7 +29,8 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
   constexpr int P = Geo::P, TF = Geo::TF, G = Geo::G;
   constexpr int H = R / 2;
   constexpr int NXH = NX / 2;
-  __shared__ V2<T> lds[G * SB * NX];
+  constexpr int SEQP = lds_padded_size(NX);
+  __shared__ V2<T> lds[G * SB * SEQP];
 
   const int tid = threadIdx.x;
   const int g = tid / TF;
@@ -38,36 +39,38 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
   const bool active = tile < N * L;
   const int f = active ? tile / L : 0;
   const int y1 = active ? tile - f * L : 0;
-  V2<T>* my = lds + g * SB * NX;
+  V2<T>* my = lds + g * SB * SEQP;
+  LdsPair lp{my, nullptr, 0, 0};
   const size_t frow = (size_t)f * R;
   const V2<T>* __restrict__ nyq = ws_nyq + ((size_t)f * L + y1) * R;
 
   // twiddle (inverse) and normalisation for row k2
   auto tw = [&](int k2) -> cx<T> { return scale(conj(twiddle<T>(tab, y1 * k2, ny)), out_scale); };
   auto row = [&](int k2) -> const V2<T>* { return ws_main + ((frow + k2) * L + y1) * NXH; };
-  const cx<T> zero{T(0), T(0)};
 
+  // Every thread issues the same unconditional loads: element m of row j for
+  // m < nx/2, element nx - m of row R - j above (at m = nx/2 that is an
+  // in-bounds neighbour, replaced below).  The kx = 0 and kx = nx/2 entries
+  // needed by the two special positions are tile-uniform loads; the special
+  // cases are then plain selects.
   cx<T> s[H][P];
 #pragma unroll
   for (int j = 1; j < H; ++j) {
     const cx<T> wj = tw(j), wc = tw(R - j);
     const V2<T>* __restrict__ rj = row(j);
     const V2<T>* __restrict__ rc = row(R - j);
+    const cx<T> zero_m = scale(wj * from2<T>(rj[0]) + conj(wc * from2<T>(rc[0])), T(0.5));
+    const cx<T> nyq_m = scale(wj * from2<T>(nyq[j]) + conj(wc * from2<T>(nyq[R - j])), T(0.5));
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int m = t + TF * i;
-      cx<T> z = zero;
-      if (active) {
-        if (i < P / 2) {
-          if (m == 0)
-            z = scale(wj * from2<T>(rj[0]) + conj(wc * from2<T>(rc[0])), T(0.5));
-          else
-            z = wj * from2<T>(rj[m]);
-        } else if (m == NXH) {
-          z = scale(wj * from2<T>(nyq[j]) + conj(wc * from2<T>(nyq[R - j])), T(0.5));
-        } else {
-          z = conj(wc * from2<T>(rc[NX - m]));
-        }
+      cx<T> z;
+      if (i < P / 2) {
+        z = wj * from2<T>(rj[m]);
+        if (i == 0) z = (t == 0) ? zero_m : z;
+      } else {
+        z = conj(wc * from2<T>(rc[NX - m]));
+        if (i == P / 2) z = (t == 0) ? nyq_m : z;
       }
       s[j][i] = z;
     }
@@ -76,27 +79,20 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
     const cx<T> w0 = tw(0), wh = tw(H);
     const V2<T>* __restrict__ r0 = row(0);
     const V2<T>* __restrict__ rh = row(H);
+    const cx<T> zero_m{(w0 * from2<T>(r0[0])).re, (wh * from2<T>(rh[0])).re};   // H_0 + i H_{R/2} at m = 0
+    const cx<T> nyq_m{(w0 * from2<T>(nyq[0])).re, (wh * from2<T>(nyq[H])).re};  // and at m = nx/2
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int m = t + TF * i;
-      cx<T> h0 = zero, hh = zero;
-      if (active) {
-        if (i < P / 2) {
-          h0 = w0 * from2<T>(r0[m]);
-          hh = wh * from2<T>(rh[m]);
-          if (m == 0) {
-            h0.im = T(0);
-            hh.im = T(0);
-          }
-        } else if (m == NXH) {
-          h0 = cx<T>{(w0 * from2<T>(nyq[0])).re, T(0)};
-          hh = cx<T>{(wh * from2<T>(nyq[H])).re, T(0)};
-        } else {
-          h0 = conj(w0 * from2<T>(r0[NX - m]));
-          hh = conj(wh * from2<T>(rh[NX - m]));
-        }
+      cx<T> z;
+      if (i < P / 2) {
+        z = w0 * from2<T>(r0[m]) + mul_pi(wh * from2<T>(rh[m]));
+        if (i == 0) z = (t == 0) ? zero_m : z;
+      } else {
+        z = conj(w0 * from2<T>(r0[NX - m])) + mul_pi(conj(wh * from2<T>(rh[NX - m])));
+        if (i == P / 2) z = (t == 0) ? nyq_m : z;
       }
-      s[0][i] = h0 + mul_pi(hh);
+      s[0][i] = z;
     }
   }
 
@@ -108,7 +104,7 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
     for (int b = 0; b < SB; ++b)
 #pragma unroll
       for (int i = 0; i < P; ++i) blk[b][i] = s[s0 + b][i];
-    fft_inverse<T, NX, P, SB>(blk, t, my, NX, 1, tab);
+    fft_inverse<T, NX, P, SB, SEQP>(blk, t, lp, 1, tab);
 #pragma unroll
     for (int b = 0; b < SB; ++b)
 #pragma unroll
@@ -137,7 +133,9 @@ template <typename T, int NX, int R>
 hipError_t launch_k3_shape(const K3Args& a, hipStream_t st) {
   using Geo = K1Geom<T, NX>;
   constexpr int H = R / 2;
-  constexpr int budget = 65536 / (Geo::G * NX * (int)sizeof(V2<T>));
+  // sequences per LDS round: keep the (padded) buffer within 80 KB so two
+  // blocks share a CU
+  constexpr int budget = 81920 / (Geo::G * lds_padded_size(NX) * (int)sizeof(V2<T>));
   constexpr int SB = budget >= H ? H : budget >= 4 ? 4 : budget >= 2 ? 2 : 1;
   const int tiles = a.N * a.L;
   const dim3 grid((tiles + Geo::G - 1) / Geo::G), block(Geo::threads);

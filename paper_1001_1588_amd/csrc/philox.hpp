@@ -38,15 +38,16 @@ __device__ __forceinline__ T uniform_open(uint32_t w) {
 // Two standard normals from two words (Box-Muller): rho (cos 2 pi u2, sin 2 pi u2).
 template <typename T> __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T& a, T& b);
 
+// float32: hardware log2, square root, and sine/cosine of 2 pi x (v_log_f32,
+// v_sqrt_f32, v_sin_f32 and v_cos_f32 take their argument in revolutions);
+// u1 >= 2^-24 keeps the logarithm finite and u2 < 1 stays in the hardware range.
 template <>
 __device__ __forceinline__ void box_muller<float>(uint32_t wa, uint32_t wb, float& a, float& b) {
   const float u1 = uniform_open<float>(wa);
   const float u2 = uniform_open<float>(wb);
-  const float rho = sqrtf(-2.0f * logf(u1));
-  float s, c;
-  sincospif(2.0f * u2, &s, &c);
-  a = rho * c;
-  b = rho * s;
+  const float rho = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u1));  // -2 ln 2 log2(u1)
+  a = rho * __builtin_amdgcn_cosf(u2);
+  b = rho * __builtin_amdgcn_sinf(u2);
 }
 
 template <>
