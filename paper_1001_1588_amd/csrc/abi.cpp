@@ -81,7 +81,7 @@ size_t dsize(int dtype) { return dtype == FFTENKF_F64 ? 8 : 4; }
 
 // Grid factorisation ny = R * L and the unit shape of the spectral sweep.
 struct Plan {
-  int R, L, P, C, units_main, units_total, pair_xcd;
+  int R, L, P, C, units_main, units_total, group_xcd;
   size_t main_elems, nyq_elems;  // complex elements of the two workspace regions
   size_t ws_bytes;
 };
@@ -105,8 +105,10 @@ Plan make_plan(int N, int ny, int nx, int dtype) {
   p.C = c;
   p.units_main = p.R * (nxh / c);
   p.units_total = p.units_main + (p.R + c - 1) / c;
-  // pair units sharing 128-byte lines on one XCD when segments are shorter
-  p.pair_xcd = ((size_t)c * 2 * dsize(dtype) < 128 && (nxh / c) % 2 == 0 && p.units_main % 16 == 0) ? 1 : 0;
+  // group the units that share 128-byte lines on one XCD when segments are shorter
+  const int seg = c * 2 * (int)dsize(dtype);
+  const int g = seg < 128 ? 128 / seg : 1;
+  p.group_xcd = (g > 1 && (nxh / c) % g == 0 && p.units_main % (8 * g) == 0) ? g : 1;
   const size_t nf = (size_t)N + 1;
   p.main_elems = nf * (size_t)ny * (size_t)nxh;
   p.nyq_elems = nf * (size_t)ny;
@@ -201,8 +203,8 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   void* ws_main = ws;
   void* ws_nyq = ws + plan.main_elems * cplx;
   if (log_enabled())
-    fprintf(stderr, "fftenkf: N=%d grid %dx%d dtype=%d R=%d L=%d C=%d units=%d pair_xcd=%d mode=%d\n", e->n_members,
-            e->ny, e->nx, e->dtype, plan.R, plan.L, plan.C, plan.units_total, plan.pair_xcd, mode);
+    fprintf(stderr, "fftenkf: N=%d grid %dx%d dtype=%d R=%d L=%d C=%d units=%d group_xcd=%d mode=%d\n", e->n_members,
+            e->ny, e->nx, e->dtype, plan.R, plan.L, plan.C, plan.units_total, plan.group_xcd, mode);
 
   const bool profiled = t_events_on && mode == K2_ANALYZE;
   if (!profiled) t_events_on = false;
@@ -226,7 +228,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   a2.C = plan.C;
   a2.units_main = plan.units_main;
   a2.units_total = plan.units_total;
-  a2.pair_xcd = plan.pair_xcd;
+  a2.group_xcd = plan.group_xcd;
   a2.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
   a2.key1 = (uint32_t)(seed >> 32);
   a2.mode = mode;

@@ -16,10 +16,10 @@
 // Main units cover kx < nx/2 ([NF][R][L][nx/2]: C adjacent kx); the Nyquist
 // column kx = nx/2 ([NF][L][R]) is covered by extra units over C adjacent k2,
 // placed first in the grid so they do not trail.  A unit's row segments are C
-// complex values; when that is less than a 128-byte line, the two units
-// sharing each line are given to blocks b and b + 8, which the hardware sends
-// to the same XCD one after the other, so the second read of every line is an
-// L2 hit rather than a second HBM fetch.
+// complex values; when that is less than a 128-byte line, the G units sharing
+// each line are given to blocks b, b + 8, .., b + 8 (G - 1), which the hardware
+// sends to the same XCD one after the other, so the later reads of every line
+// are L2 hits rather than further HBM fetches.
 #pragma once
 
 #include <float.h>
@@ -78,9 +78,10 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   const int units_nyq = a.units_total - a.units_main;
   if (unit >= units_nyq) {
     int um = unit - units_nyq;
-    if (a.pair_xcd) {
+    if (a.group_xcd > 1) {
+      const int G = a.group_xcd;  // a power of two
       const int x = um & 7, q = um >> 3;
-      um = 2 * (((q >> 1) << 3) + x) + (q & 1);
+      um = G * (((q / G) << 3) + x) + (q & (G - 1));
     }
     const int nchunk = nxh / C;
     k2 = um / nchunk;

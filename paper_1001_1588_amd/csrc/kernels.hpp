@@ -38,7 +38,7 @@ struct K2Args {
   const void* R_spec;  // [ny][nx/2+1] or nullptr
   double r_scalar;
   int N, ny, nx, R, L, C, units_main, units_total;
-  int pair_xcd;  // blocks b and b+8 take adjacent kx chunks of one k2 (see the spectral sweep)
+  int group_xcd;  // G > 1: blocks b, b+8, .., b+8(G-1) take G adjacent kx chunks of one k2
   uint32_t key0, key1;
   int mode;
   void* dbg_chat;  // [ny][nx/2+1] real
