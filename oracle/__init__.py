@@ -9,7 +9,9 @@ Filter with application to a coupled atmosphere-wildland fire model":
 * philox.py -- Philox4x32-10 and Box-Muller from their published definitions,
                for the perturbations e_k ~ N(0, R) of eq. (1);
 * enkf.py   -- O1, the spectral form (eq. (2) and eq. (3)), and O2, the dense
-               form (eq. (1) with the circulant lag-averaged sample covariance).
+               form (eq. (1) with the circulant lag-averaged sample covariance);
+* learned.py -- the learned spectral covariance: a per-wavenumber perceptron
+               whose estimate replaces the c_hat of eq. (2) in eq. (3).
 
 Only the tests, the smoke check and the benchmark's CPU baseline may import
 this package.  It shares no code with the HIP path and imports nothing from it.

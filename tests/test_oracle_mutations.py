@@ -14,7 +14,8 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PIN_TESTS = ["test_oracle_dft.py", "test_oracle_variance.py", "test_oracle_update.py", "test_oracle_rng.py"]
+PIN_TESTS = ["test_oracle_dft.py", "test_oracle_variance.py", "test_oracle_update.py", "test_oracle_rng.py",
+             "test_oracle_learned.py"]
 
 MUTANTS = [
     ("enkf.py", "sum(axis=0) / (N - 1)", "sum(axis=0) / N"),
@@ -34,6 +35,14 @@ MUTANTS = [
     ("philox.py", "hi1 ^ x[1] ^ k0, lo1, hi0 ^ x[3] ^ k1", "hi1 ^ x[1] ^ k1, lo1, hi0 ^ x[3] ^ k0"),
     ("philox.py", "np.sqrt(-2.0 * np.log(u1))", "np.sqrt(-1.0 * np.log(u1))"),
     ("philox.py", "ang = 2.0 * np.pi * u2", "ang = np.pi * u2"),
+    ("learned.py", "full[:, kx] = c_half[ky, nx - kx]", "full[:, kx] = c_half[:, nx - kx]"),
+    ("learned.py", "dy, dx = j // 5 - 2, j % 5 - 2", "dx, dy = j // 5 - 2, j % 5 - 2"),
+    ("learned.py", "np.log(full / mu + EPS)", "np.log(full + EPS)"),
+    ("learned.py", "np.minimum(ky, ny - ky)", "ky + 0 * np.minimum(ky, ny - ky)"),
+    ("learned.py", "+ lsb) >> np.uint64(16)", ") >> np.uint64(16)"),
+    ("learned.py", "h = np.maximum(h @ W + b, 0.0)", "h = np.maximum(h @ W.T + b, 0.0)"),
+    ("learned.py", "return mu * np.exp(y), mu", "return np.exp(y), mu"),
+    ("learned.py", "K = spectral_gain(lam, R_spec, tiny)", "K = spectral_gain(c_hat, R_spec, tiny)"),
 ]
 
 
