@@ -87,9 +87,39 @@ typedef struct fftenkf_ens {
  */
 int fftenkf_analyze(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed, void* out);
 
-/* Bytes of workspace fftenkf_analyze needs: (N+1) spectra of ny*(nx/2+1) complex
- * values plus one ny*(nx/2+1) real plane, rounded up to 256; 0 if the shape is invalid. */
+/* Bytes of workspace fftenkf_analyze and fftenkf_analyze_learned need: (N+1)
+ * spectra of ny*(nx/2+1) complex values, two ny*(nx/2+1) real planes and one
+ * float per unit of the spectral sweep, rounded up to 256; 0 if the shape is invalid. */
 size_t fftenkf_workspace_bytes(int n_members, int ny, int nx, int dtype);
+
+/*
+ * Learned spectral covariance: a per-wavenumber perceptron replaces the
+ * estimator of eq. (2) in eq. (3).  For each stored bin it reads
+ * x_j = log(c_hat(ky + dy, kx + dx) / mu + 1e-6), (dy, dx) = (j/5 - 2, j%5 - 2),
+ * j < 25 (indices on the full periodic spectrum, c_hat even), and
+ * x_25 = log(1 + |k|) with |k| = sqrt(min(ky, ny-ky)^2 + kx^2); then
+ * h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), h3 = relu(h2 W3 + b3),
+ * y = h3 . w4 + b4 and lambda_hat = mu exp(y), mu = mean of c_hat over the
+ * ny*(nx/2+1) stored bins.  The gain is lambda_hat / (lambda_hat + R_spec).
+ * Inputs, weights and hidden activations are rounded to bfloat16 (nearest,
+ * ties to even); products accumulate in float32 on the matrix cores.
+ * All eight pointers are device float32 arrays, row-major [in][out].
+ */
+typedef struct fftenkf_mlp {
+  const float* W1; /* [26][64] */
+  const float* b1; /* [64] */
+  const float* W2; /* [64][64] */
+  const float* b2; /* [64] */
+  const float* W3; /* [64][64] */
+  const float* b3; /* [64] */
+  const float* w4; /* [64] */
+  const float* b4; /* [1] */
+} fftenkf_mlp;
+
+/* As fftenkf_analyze, with lambda_hat from the perceptron in place of c_hat
+ * (float32 only).  Same arguments, ownership and error behaviour. */
+int fftenkf_analyze_learned(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed,
+                            const fftenkf_mlp* mlp, void* out);
 
 /* Largest N the analysis supports for a dtype. */
 int fftenkf_max_members(int dtype);
@@ -116,6 +146,11 @@ int fftenkf_debug_spectra(const fftenkf_ens* ens, const void* data, const void* 
 int fftenkf_debug_perturb(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed,
                           void* e_hat);
 void fftenkf_debug_fail_next(int status);
+
+/* Test-only: c_hat (eq. (2)) and lambda_hat (the perceptron) per stored bin,
+ * device [ny][nx/2+1] float each, and mu (device, one float); float32 only. */
+int fftenkf_debug_learned_spectrum(const fftenkf_ens* ens, const void* data, const fftenkf_mlp* mlp, void* c_hat,
+                                   void* lam_hat, void* mu);
 
 /*
  * Profiling hook for the calling thread: with n == 4, the next fftenkf_analyze

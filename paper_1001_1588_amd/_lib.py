@@ -35,6 +35,15 @@ class Ens(ctypes.Structure):
     ]
 
 
+class Mlp(ctypes.Structure):
+    """Mirror of struct fftenkf_mlp (eight device float32 pointers)."""
+
+    _fields_ = [(name, ctypes.c_void_p) for name in ("W1", "b1", "W2", "b2", "W3", "b3", "w4", "b4")]
+
+
+MLP_SHAPES = {"W1": (26, 64), "b1": (64,), "W2": (64, 64), "b2": (64,), "W3": (64, 64), "b3": (64,),
+              "w4": (64,), "b4": (1,)}
+
 _lib: Optional[ctypes.CDLL] = None
 
 EXPORTS = {
@@ -49,6 +58,10 @@ EXPORTS = {
                                              ctypes.c_void_p]),
     "fftenkf_debug_fail_next": (None, [ctypes.c_int]),
     "fftenkf_profile_events": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+    "fftenkf_analyze_learned": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                               ctypes.POINTER(Mlp), ctypes.c_void_p]),
+    "fftenkf_debug_learned_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.POINTER(Mlp),
+                                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -159,6 +172,52 @@ def debug_perturb(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Ten
                                      ctypes.c_uint64(seed & (2**64 - 1)), out.data_ptr())
     _check(st, "fftenkf_debug_perturb")
     return out
+
+
+def mlp_weights(weights: dict, device) -> dict:
+    """Device float32 copies of the perceptron's weights (W1 [26, 64] .. b4 [1])."""
+    out = {}
+    for name, shape in MLP_SHAPES.items():
+        t = torch.as_tensor(weights[name], dtype=torch.float32).reshape(shape)
+        out[name] = t.to(device).contiguous()
+    return out
+
+
+def _mlp_struct(w: dict) -> Mlp:
+    for name, shape in MLP_SHAPES.items():
+        t = w[name]
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == shape):
+            raise ValueError(f"mlp weight {name} must be a contiguous float32 device tensor of shape {shape}")
+    return Mlp(**{name: w[name].data_ptr() for name in MLP_SHAPES})
+
+
+def analyze_learned(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, float], seed: int,
+                    weights: dict, out: Optional[torch.Tensor] = None,
+                    workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Eq. (3) with the perceptron's lambda_hat in place of c_hat (float32); weights from mlp_weights."""
+    R_t, r = _rspec(R_spec)
+    e, ws = _make_ens(ens, workspace, r)
+    m = _mlp_struct(weights)
+    if out is None:
+        out = torch.empty_like(ens)
+    st = lib().fftenkf_analyze_learned(ctypes.byref(e), data.data_ptr(), _ptr(R_t),
+                                       ctypes.c_uint64(seed & (2**64 - 1)), ctypes.byref(m), out.data_ptr())
+    _check(st, "fftenkf_analyze_learned")
+    return out
+
+
+def debug_learned_spectrum(ens: torch.Tensor, data: torch.Tensor, weights: dict):
+    """(c_hat, lambda_hat, mu): the sample spectrum, the perceptron's estimate and the mean of c_hat."""
+    e, ws = _make_ens(ens, None, 0.0)
+    m = _mlp_struct(weights)
+    N, ny, nx = ens.shape
+    c_hat = torch.empty((ny, nx // 2 + 1), dtype=torch.float32, device=ens.device)
+    lam = torch.empty_like(c_hat)
+    mu = torch.empty(1, dtype=torch.float32, device=ens.device)
+    st = lib().fftenkf_debug_learned_spectrum(ctypes.byref(e), data.data_ptr(), ctypes.byref(m), c_hat.data_ptr(),
+                                              lam.data_ptr(), mu.data_ptr())
+    _check(st, "fftenkf_debug_learned_spectrum")
+    return c_hat, lam, mu
 
 
 def debug_fail_next(status: int) -> None:

@@ -82,9 +82,12 @@ size_t dsize(int dtype) { return dtype == FFTENKF_F64 ? 8 : 4; }
 // Grid factorisation ny = R * L and the unit shape of the spectral sweep.
 struct Plan {
   int R, L, P, C, units_main, units_total, group_xcd;
-  size_t main_elems, nyq_elems;  // complex elements of the two workspace regions
+  size_t main_elems, nyq_elems;  // complex elements of the two spectral regions
+  size_t off_nyq, off_chat, off_lam, off_part;  // byte offsets in the workspace
   size_t ws_bytes;
 };
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
 int rows_per_tile(int dtype, int nx) {
   if (dtype == FFTENKF_F32) return nx <= 2048 ? 16 : 8;
@@ -113,8 +116,12 @@ Plan make_plan(int N, int ny, int nx, int dtype) {
   p.main_elems = nf * (size_t)ny * (size_t)nxh;
   p.nyq_elems = nf * (size_t)ny;
   const size_t cplx = 2 * dsize(dtype);
-  size_t bytes = (p.main_elems + p.nyq_elems) * cplx + (size_t)ny * (size_t)(nxh + 1) * dsize(dtype);
-  p.ws_bytes = (bytes + 255) / 256 * 256;
+  const size_t plane = (size_t)ny * (size_t)(nxh + 1) * dsize(dtype);
+  p.off_nyq = p.main_elems * cplx;
+  p.off_chat = round256(p.off_nyq + p.nyq_elems * cplx);
+  p.off_lam = round256(p.off_chat + plane);
+  p.off_part = round256(p.off_lam + plane);
+  p.ws_bytes = round256(p.off_part + (size_t)p.units_total * sizeof(float));
   return p;
 }
 
@@ -187,8 +194,11 @@ bool log_enabled() {
 }
 
 // Enqueue sweeps 1 and 2 (mode) and, for an analysis, sweep 3.
+// With mlp, sweep 2 runs twice around the perceptron: K2_STATS, then (for an
+// analysis) K2_UPDATE_LEARNED; mlp_chat/mlp_lam/mlp_mu request the spectra only.
 int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_spec, uint64_t seed, void* out,
-        int mode, void* dbg_chat, void* dbg_gain, void* dbg_spec, void* dbg_e) {
+        int mode, void* dbg_chat, void* dbg_gain, void* dbg_spec, void* dbg_e, const fftenkf_mlp* mlp = nullptr,
+        void* mlp_chat = nullptr, void* mlp_lam = nullptr, void* mlp_mu = nullptr) {
   if (t_fail_next != 0) {
     const int st = t_fail_next;
     t_fail_next = 0;
@@ -201,12 +211,13 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   const size_t cplx = 2 * dsize(e->dtype);
   char* ws = static_cast<char*>(e->workspace);
   void* ws_main = ws;
-  void* ws_nyq = ws + plan.main_elems * cplx;
+  void* ws_nyq = ws + plan.off_nyq;
+  (void)cplx;
   if (log_enabled())
     fprintf(stderr, "fftenkf: N=%d grid %dx%d dtype=%d R=%d L=%d C=%d units=%d group_xcd=%d mode=%d\n", e->n_members,
             e->ny, e->nx, e->dtype, plan.R, plan.L, plan.C, plan.units_total, plan.group_xcd, mode);
 
-  const bool profiled = t_events_on && mode == K2_ANALYZE;
+  const bool profiled = t_events_on && mode == K2_ANALYZE && mlp == nullptr;
   if (!profiled) t_events_on = false;
   err = mark(0, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "profile event: %s", hipGetErrorString(err));
@@ -237,7 +248,38 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   a2.dbg_spec = dbg_spec;
   a2.dbg_e = dbg_e;
   a2.tab = tab;
-  err = e->dtype == FFTENKF_F32 ? launch_k2_f32(a2, stream) : launch_k2_f64(a2, stream);
+  if (mlp != nullptr) {
+    // the perceptron needs c_hat of every bin, and their mean, before any update
+    a2.mode = K2_STATS;
+    a2.chat_map = mlp_chat != nullptr ? mlp_chat : ws + plan.off_chat;
+    a2.partials = ws + plan.off_part;
+    err = launch_k2_f32(a2, stream);
+    if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 2 (statistics) launch: %s", hipGetErrorString(err));
+    K7Args a7{};
+    a7.chat = static_cast<const float*>(a2.chat_map);
+    a7.partials = static_cast<const float*>(a2.partials);
+    a7.n_partials = plan.units_total;
+    a7.ny = e->ny;
+    a7.nx = e->nx;
+    a7.W1 = mlp->W1;
+    a7.b1 = mlp->b1;
+    a7.W2 = mlp->W2;
+    a7.b2 = mlp->b2;
+    a7.W3 = mlp->W3;
+    a7.b3 = mlp->b3;
+    a7.w4 = mlp->w4;
+    a7.b4 = mlp->b4;
+    a7.lam = static_cast<float*>(mlp_lam != nullptr ? mlp_lam : ws + plan.off_lam);
+    a7.mu_out = static_cast<float*>(mlp_mu);
+    err = launch_k7(a7, stream);
+    if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "perceptron launch: %s", hipGetErrorString(err));
+    if (mode != K2_ANALYZE) return FFTENKF_OK;
+    a2.mode = K2_UPDATE_LEARNED;
+    a2.lam_map = a7.lam;
+    err = launch_k2_f32(a2, stream);
+  } else {
+    err = e->dtype == FFTENKF_F32 ? launch_k2_f32(a2, stream) : launch_k2_f64(a2, stream);
+  }
   if (err == hipSuccess) err = mark(2, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 2 launch: %s", hipGetErrorString(err));
   if (mode != K2_ANALYZE) return FFTENKF_OK;
@@ -248,6 +290,61 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   t_events_on = false;
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 3 launch: %s", hipGetErrorString(err));
   return FFTENKF_OK;
+}
+
+// The eight weight arrays of the perceptron: present and aligned (host-side
+// checks), then device memory of the current device.
+int check_mlp(const fftenkf_mlp* m, bool device) {
+  const Ptr w[] = {{m->W1, 26 * 64 * 4, "mlp.W1"}, {m->b1, 64 * 4, "mlp.b1"}, {m->W2, 64 * 64 * 4, "mlp.W2"},
+                   {m->b2, 64 * 4, "mlp.b2"},      {m->W3, 64 * 64 * 4, "mlp.W3"}, {m->b3, 64 * 4, "mlp.b3"},
+                   {m->w4, 64 * 4, "mlp.w4"},      {m->b4, 4, "mlp.b4"}};
+  for (const Ptr& p : w) {
+    if (p.p == nullptr) return fail(FFTENKF_EINVAL, "%s is NULL", p.name);
+    if (misaligned(p.p, 4)) return fail(FFTENKF_EINVAL, "%s is not 4-byte aligned", p.name);
+  }
+  return device ? check_pointers(w, 8) : FFTENKF_OK;
+}
+
+int analyze_impl(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed, const fftenkf_mlp* mlp,
+                 void* out) {
+  try {
+    Plan plan;
+    int st = validate_shape(e, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (data == nullptr) return fail(FFTENKF_EINVAL, "data is NULL");
+    if (out == nullptr) return fail(FFTENKF_EINVAL, "out is NULL");
+    if (misaligned(data, 16) || misaligned(out, 16) || (R_spec != nullptr && misaligned(R_spec, 16)))
+      return fail(FFTENKF_EINVAL, "data, R_spec and out must be 16-byte aligned");
+    if (R_spec == nullptr && !(e->r_scalar >= 0.0))
+      return fail(FFTENKF_EINVAL, "r_scalar must be >= 0 when R_spec is NULL");
+    const size_t s = dsize(e->dtype);
+    const size_t field = (size_t)e->ny * e->nx * s;
+    const size_t ens_b = field * e->n_members;
+    const size_t rs_b = (size_t)e->ny * (e->nx / 2 + 1) * s;
+    const Ptr ptrs[] = {{e->members, ens_b, "members"},
+                        {data, field, "data"},
+                        {R_spec, rs_b, "R_spec"},
+                        {out, ens_b, "out"},
+                        {e->workspace, plan.ws_bytes, "workspace"}};
+    const int np = 5;
+    for (int i = 0; i < np; ++i)
+      for (int j = i + 1; j < np; ++j) {
+        if (ptrs[i].p == nullptr || ptrs[j].p == nullptr) continue;
+        const bool in_place = (i == 0 && j == 3 && ptrs[i].p == ptrs[j].p);
+        if (!in_place && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+      }
+    if (mlp != nullptr) {
+      st = check_mlp(mlp, false);
+      if (st != FFTENKF_OK) return st;
+    }
+    st = check_pointers(ptrs, np);
+    if (st == FFTENKF_OK && mlp != nullptr) st = check_mlp(mlp, true);
+    if (st != FFTENKF_OK) return st;
+    return run(e, plan, data, R_spec, seed, out, K2_ANALYZE, nullptr, nullptr, nullptr, nullptr, mlp);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
 }
 
 }  // namespace
@@ -299,39 +396,14 @@ int fftenkf_profile_events(void* const* events, int n) {
 }
 
 int fftenkf_analyze(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed, void* out) {
-  try {
-    Plan plan;
-    int st = validate_shape(e, &plan);
-    if (st != FFTENKF_OK) return st;
-    if (data == nullptr) return fail(FFTENKF_EINVAL, "data is NULL");
-    if (out == nullptr) return fail(FFTENKF_EINVAL, "out is NULL");
-    if (misaligned(data, 16) || misaligned(out, 16) || (R_spec != nullptr && misaligned(R_spec, 16)))
-      return fail(FFTENKF_EINVAL, "data, R_spec and out must be 16-byte aligned");
-    if (R_spec == nullptr && !(e->r_scalar >= 0.0))
-      return fail(FFTENKF_EINVAL, "r_scalar must be >= 0 when R_spec is NULL");
-    const size_t s = dsize(e->dtype);
-    const size_t field = (size_t)e->ny * e->nx * s;
-    const size_t ens_b = field * e->n_members;
-    const size_t rs_b = (size_t)e->ny * (e->nx / 2 + 1) * s;
-    const Ptr ptrs[] = {{e->members, ens_b, "members"},
-                        {data, field, "data"},
-                        {R_spec, rs_b, "R_spec"},
-                        {out, ens_b, "out"},
-                        {e->workspace, plan.ws_bytes, "workspace"}};
-    const int np = 5;
-    for (int i = 0; i < np; ++i)
-      for (int j = i + 1; j < np; ++j) {
-        if (ptrs[i].p == nullptr || ptrs[j].p == nullptr) continue;
-        const bool in_place = (i == 0 && j == 3 && ptrs[i].p == ptrs[j].p);
-        if (!in_place && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
-          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
-      }
-    st = check_pointers(ptrs, np);
-    if (st != FFTENKF_OK) return st;
-    return run(e, plan, data, R_spec, seed, out, K2_ANALYZE, nullptr, nullptr, nullptr, nullptr);
-  } catch (...) {
-    return fail(FFTENKF_EDEVICE, "internal error");
-  }
+  return analyze_impl(e, data, R_spec, seed, nullptr, out);
+}
+
+int fftenkf_analyze_learned(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed,
+                            const fftenkf_mlp* mlp, void* out) {
+  if (mlp == nullptr) return fail(FFTENKF_EINVAL, "mlp is NULL");
+  if (e != nullptr && e->dtype != FFTENKF_F32) return fail(FFTENKF_EUNSUPPORTED, "the learned covariance is float32 only");
+  return analyze_impl(e, data, R_spec, seed, mlp, out);
 }
 
 int fftenkf_debug_spectra(const fftenkf_ens* e, const void* data, const void* R_spec, void* c_hat, void* gain,
@@ -382,6 +454,37 @@ int fftenkf_debug_perturb(const fftenkf_ens* e, const void* data, const void* R_
     st = check_pointers(ptrs, 5);
     if (st != FFTENKF_OK) return st;
     return run(e, plan, data, R_spec, seed, nullptr, K2_DEBUG_PERTURB, nullptr, nullptr, nullptr, e_hat);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+int fftenkf_debug_learned_spectrum(const fftenkf_ens* e, const void* data, const fftenkf_mlp* mlp, void* c_hat,
+                                   void* lam_hat, void* mu) {
+  try {
+    Plan plan;
+    int st = validate_shape(e, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (e->dtype != FFTENKF_F32) return fail(FFTENKF_EUNSUPPORTED, "the learned covariance is float32 only");
+    if (mlp == nullptr || data == nullptr || c_hat == nullptr || lam_hat == nullptr || mu == nullptr)
+      return fail(FFTENKF_EINVAL, "data, mlp, c_hat, lam_hat and mu are required");
+    const size_t plane = (size_t)e->ny * (e->nx / 2 + 1) * 4;
+    const Ptr ptrs[] = {{e->members, (size_t)e->ny * e->nx * 4 * e->n_members, "members"},
+                        {data, (size_t)e->ny * e->nx * 4, "data"},
+                        {c_hat, plane, "c_hat"},
+                        {lam_hat, plane, "lam_hat"},
+                        {mu, 4, "mu"},
+                        {e->workspace, plan.ws_bytes, "workspace"}};
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j)
+        if (overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+    st = check_mlp(mlp, false);
+    if (st == FFTENKF_OK) st = check_pointers(ptrs, 6);
+    if (st == FFTENKF_OK) st = check_mlp(mlp, true);
+    if (st != FFTENKF_OK) return st;
+    return run(e, plan, data, nullptr, 0, nullptr, K2_STATS, nullptr, nullptr, nullptr, nullptr, mlp, c_hat, lam_hat,
+               mu);
   } catch (...) {
     return fail(FFTENKF_EDEVICE, "internal error");
   }

@@ -128,7 +128,9 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
     for (int i = 0; i < P; ++i) dv[0][i] = from2<T>(ld_off(fb, voff[i]));
   }
 
-  // forward length-L transforms
+  // forward length-L transforms (the learned update starts from transformed fields)
+  const bool transformed = a.mode == K2_UPDATE_LEARNED;
+  if (!transformed) {
 #pragma unroll
   for (int f0 = 0; f0 < NMAX; f0 += FB) {
     if (f0 < N) {
@@ -145,6 +147,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
     }
   }
   fft_forward<T, L, P, 1, SEQP>(dv, t2, lp, C, tab);
+  }
   const bool valid_w = valid;
 
   // ---- eq. (2) per bin, then the gain of eq. (3)
@@ -154,6 +157,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   const T* __restrict__ Rspec = static_cast<const T*>(a.R_spec);
   T gain[P], amp[P];
   int ky[P];
+  T csum = T(0);
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     ky[i] = k2 + R * (t2 + TF2 * i);
@@ -169,11 +173,16 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
         const cx<T> d = u[f][i] - mean;
         var += d.re * d.re + d.im * d.im;
       }
-    const T chat = var * var_scale;
+    T chat = var * var_scale;
+    if (transformed && valid_w) chat = static_cast<const T*>(a.lam_map)[(size_t)ky[i] * nh + kx];
     T rb = T(a.r_scalar);
     if (Rspec != nullptr && valid_w) rb = Rspec[(size_t)ky[i] * nh + kx];
     const T den = chat + rb;
     gain[i] = den < tiny_normal<T>() ? T(0) : chat / den;
+    if (a.mode == K2_STATS) {
+      if (valid_w) static_cast<T*>(a.chat_map)[(size_t)ky[i] * nh + kx] = chat;
+      csum += valid_w ? chat : T(0);
+    }
     amp[i] = sqrt_t<T>(n_tot * rb);
     if (a.mode == K2_DEBUG_SPECTRA && valid_w) {
       const size_t bin = (size_t)ky[i] * nh + kx;
@@ -191,6 +200,31 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
     }
   }
   if (a.mode == K2_DEBUG_SPECTRA) return;  // no synchronisation follows
+  if (a.mode == K2_STATS) {
+    // transformed fields back in place, and this block's sum of c_hat
+    if (valid) {
+#pragma unroll
+      for (int f = 0; f < NMAX; ++f)
+        if (f < N) {
+          V2<T>* fb = ubase + (size_t)f * fstride;
+#pragma unroll
+          for (int i = 0; i < P; ++i) st_off(fb, voff[i], to2<T>(u[f][i]));
+        }
+      V2<T>* fb = ubase + (size_t)N * fstride;
+#pragma unroll
+      for (int i = 0; i < P; ++i) st_off(fb, voff[i], to2<T>(dv[0][i]));
+    }
+    T* red = reinterpret_cast<T*>(k2_lds_raw);
+    __syncthreads();  // the exchange buffers are free again
+    red[tid] = csum;
+    __syncthreads();
+    if (tid == 0) {
+      T tot = T(0);
+      for (int k = 0; k < (int)blockDim.x; ++k) tot += red[k];
+      static_cast<float*>(a.partials)[unit] = (float)tot;
+    }
+    return;
+  }
 
   // ---- perturbations and update, two members per Philox call
   const bool edge = (kx == 0) || (kx == nxh);

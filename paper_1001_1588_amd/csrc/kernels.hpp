@@ -30,7 +30,12 @@ struct K1Args {
   const void* tab;  // W_4096^k table of dtype's complex type (device)
 };
 
-enum K2Mode { K2_ANALYZE = 0, K2_DEBUG_SPECTRA = 1, K2_DEBUG_PERTURB = 2 };
+// K2_STATS: forward transforms and eq. (2) only -- writes c_hat to chat_map,
+//   one partial sum of c_hat per block to partials, and the transformed fields
+//   back in place.
+// K2_UPDATE_LEARNED: starts from those transformed fields and takes the gain
+//   from lam_map (an estimate of the eigenvalues) instead of eq. (2).
+enum K2Mode { K2_ANALYZE = 0, K2_DEBUG_SPECTRA = 1, K2_DEBUG_PERTURB = 2, K2_STATS = 3, K2_UPDATE_LEARNED = 4 };
 
 struct K2Args {
   void* ws_main;
@@ -45,6 +50,9 @@ struct K2Args {
   void* dbg_gain;  // [ny][nx/2+1] real
   void* dbg_spec;  // [N+1][ny][nx/2+1] complex, or nullptr
   void* dbg_e;     // [N][ny][nx/2+1] complex
+  void* chat_map;  // [ny][nx/2+1] real (K2_STATS)
+  void* partials;  // [units_total] float (K2_STATS)
+  const void* lam_map;  // [ny][nx/2+1] real (K2_UPDATE_LEARNED)
   const void* tab;
 };
 
@@ -70,6 +78,26 @@ hipError_t launch_k2_f32(const K2Args& a, hipStream_t s);
 hipError_t launch_k2_f64(const K2Args& a, hipStream_t s);
 hipError_t launch_k3_f32(const K3Args& a, hipStream_t s);
 hipError_t launch_k3_f64(const K3Args& a, hipStream_t s);
+
+// Learned spectral covariance (float32): lambda_hat per stored bin from the
+// sample spectrum c_hat by a perceptron on matrix cores.
+struct K7Args {
+  const float* chat;      // [ny][nx/2+1]
+  const float* partials;  // [n_partials] partial sums of chat
+  int n_partials;
+  int ny, nx;
+  const float* W1;  // [26][64]
+  const float* b1;  // [64]
+  const float* W2;  // [64][64]
+  const float* b2;  // [64]
+  const float* W3;  // [64][64]
+  const float* b3;  // [64]
+  const float* w4;  // [64]
+  const float* b4;  // [1]
+  float* lam;       // [ny][nx/2+1]
+  float* mu_out;    // [1] or nullptr
+};
+hipError_t launch_k7(const K7Args& a, hipStream_t s);
 
 // Device address of the W_4096^k table (float2 for dtype 0, double2 for 1) on
 // the current device, filled from float64 host values on first use.

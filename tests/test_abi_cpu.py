@@ -82,12 +82,46 @@ def test_partial_overlap_rejected(built_lib):
     assert call(_ens(workspace=0x100000 + 256)) == _lib.EINVAL          # workspace overlaps members
 
 
+def _mlp(**kw):
+    d = {name: 0x900000 + 0x10000 * i for i, name in enumerate(_lib.MLP_SHAPES)}
+    d.update(kw)
+    return _lib.Mlp(**d)
+
+
+def call_learned(e, mlp, data=0x200000, out=0x300000):
+    lib = _lib.lib()
+    return lib.fftenkf_analyze_learned(ctypes.byref(e), data, None, 1, ctypes.byref(mlp) if mlp is not None else None,
+                                       out)
+
+
+def test_learned_validation(built_lib):
+    assert call_learned(_ens(), None) == _lib.EINVAL
+    assert call_learned(_ens(dtype=_lib.F64), _mlp()) == _lib.EUNSUPPORTED
+    assert call_learned(_ens(), _mlp(W2=None)) == _lib.EINVAL
+    assert "W2" in _lib.lib().fftenkf_last_error().decode()
+    assert call_learned(_ens(), _mlp(b4=0x900002)) == _lib.EINVAL          # misaligned
+    assert call_learned(_ens(n_members=25), _mlp()) == _lib.EUNSUPPORTED
+    lib = _lib.lib()
+    e = _ens()
+    assert lib.fftenkf_debug_learned_spectrum(ctypes.byref(e), 0x200000, None, 0x300000, 0x400000,
+                                              0x500000) == _lib.EINVAL
+    e64 = _ens(dtype=_lib.F64)
+    assert lib.fftenkf_debug_learned_spectrum(ctypes.byref(e64), 0x200000, ctypes.byref(_mlp()), 0x300000,
+                                              0x400000, 0x500000) == _lib.EUNSUPPORTED
+
+
 def test_workspace_formula(built_lib):
     lib = _lib.lib()
     for (N, ny, nx, dt, s) in [(20, 2048, 2048, 0, 4), (5, 64, 64, 1, 8), (2, 8, 8, 0, 4), (24, 4096, 4096, 0, 4)]:
         nh = nx // 2 + 1
-        raw = (N + 1) * ny * nh * 2 * s + ny * nh * s
-        assert lib.fftenkf_workspace_bytes(N, ny, nx, dt) == (raw + 255) // 256 * 256
+        r256 = lambda b: (b + 255) // 256 * 256  # noqa: E731
+        # spectra of the N+1 fields, then c_hat and lambda_hat planes, then one float per unit
+        R = min(ny, (16 if nx <= 2048 else 8) if dt == 0 else (8 if nx <= 2048 else 4))
+        L = ny // R
+        C = min(nx // 2, 256 // (L // min(4, L)))
+        units = R * (nx // 2 // C) + (R + C - 1) // C
+        raw = r256(r256(r256((N + 1) * ny * nh * 2 * s) + ny * nh * s) + ny * nh * s) + 4 * units
+        assert lib.fftenkf_workspace_bytes(N, ny, nx, dt) == r256(raw)
     assert lib.fftenkf_workspace_bytes(1, 8, 8, 0) == 0
     assert lib.fftenkf_workspace_bytes(4, 8, 12, 0) == 0
     assert lib.fftenkf_workspace_bytes(4, 8, 8, 3) == 0

@@ -1,0 +1,168 @@
+"""Learned spectral covariance on the GPU against oracle/learned.py, through the C ABI.
+
+The kernel computes c_hat in float32 from float32 fields; the oracle in float64.
+What the comparison can demand follows from that:
+
+* c_hat and mu: the plain path's bar, relative L2 <= 1e-5;
+* a network that returns feature j (one-hot first layer, +-1 weights, exact in
+  bfloat16): the kernel's y is bf16(x_j) computed from its own c_hat, the
+  oracle's is bf16(x_j) from its c_hat.  bfloat16 rounding is monotone, so
+  |y_gpu - y_ref| <= |x_gpu - x_ref| + ulp_bf16(x) <= 2^-7 |x| + 1e-3 (the
+  float32 log of c_hat / mu + 1e-6 differs from float64 by less than 1e-3 on
+  these spectra, c_hat / mu >= 1e-5); and, a rounding boundary being rarely
+  straddled, at least 98% of the bins agree exactly;
+* a random network: a straddled boundary in one of the 218 roundings of a bin
+  moves y by at most one bf16 ulp of that value times the network's gain after
+  it, so a few bins differ by up to ~1e-2 while the rest agree to float32
+  accumulation order (~1e-5); the test asserts the 99th percentile of |dy|
+  <= 1e-2, the maximum <= 0.1 and the relative L2 of lambda_hat <= 5e-3;
+* the learned analysis: the gain moves by K(1-K) dy <= dy / 4 at each bin, so
+  the analysis ensemble agrees to relative L2 <= 2e-4.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import dft, enkf, learned
+from paper_1001_1588_amd import _lib, twin
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def random_weights(seed, scale=0.7):
+    rng = np.random.default_rng(seed)
+    he = lambda fan_in, shape: rng.standard_normal(shape) * scale * np.sqrt(2.0 / fan_in)  # noqa: E731
+    return dict(W1=he(26, (26, 64)), b1=rng.standard_normal(64) * 0.1, W2=he(64, (64, 64)),
+                b2=rng.standard_normal(64) * 0.1, W3=he(64, (64, 64)), b3=rng.standard_normal(64) * 0.1,
+                w4=he(64, (64,)), b4=rng.standard_normal(1) * 0.1)
+
+
+def one_hot_weights(j):
+    """y = feature j exactly: h = (relu(x_j), relu(-x_j)), y = h0 - h1."""
+    w = {k: np.zeros(s) for k, s in _lib.MLP_SHAPES.items()}
+    w["W1"][j, 0], w["W1"][j, 1] = 1.0, -1.0
+    w["W2"][0, 0] = w["W2"][1, 1] = w["W3"][0, 0] = w["W3"][1, 1] = 1.0
+    w["w4"][0], w["w4"][1] = 1.0, -1.0
+    return w
+
+
+def gpu_spectrum(tw, w):
+    ens, data = to_dev(tw.ens), to_dev(tw.data)
+    c, lam, mu = _lib.debug_learned_spectrum(ens, data, _lib.mlp_weights(w, DEV))
+    torch.cuda.synchronize()
+    return c.cpu().numpy().astype(np.float64), lam.cpu().numpy().astype(np.float64), float(mu.item())
+
+
+def oracle_c_hat(tw, method):
+    _, c = enkf.spectral_mean_variance(dft.rdft2(tw.ens.astype(np.float64), method=method))
+    return c
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+# (ny, nx, N, R kind)
+CASES = [(8, 8, 2, "scalar"), (16, 16, 4, "spectral"), (64, 128, 5, "scalar"), (256, 64, 5, "spectral"),
+         (128, 512, 8, "scalar"), (512, 512, 5, "spectral"), (32, 2048, 5, "scalar")]
+
+
+def case_twin(ny, nx, N, R_kind):
+    return twin.random_ensemble(ny, nx, N, seed=7 * ny + 3 * nx + N, dtype=np.float32, r=0.05, R_kind=R_kind)
+
+
+def method_for(ny, nx):
+    return "matmul" if ny * nx <= 65536 else "fft"
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}-N{c[2]}")
+def test_sample_spectrum_and_mean(case):
+    tw = case_twin(*case)
+    c_gpu, _, mu_gpu = gpu_spectrum(tw, random_weights(1))
+    c_ref = oracle_c_hat(tw, method_for(*case[:2]))
+    assert rel_l2(c_gpu, c_ref) <= 1e-5
+    assert abs(mu_gpu - c_ref.mean()) <= 1e-5 * c_ref.mean()
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 3), (16, 32, 4), (64, 16, 5)], ids=str)
+def test_every_feature_lands_where_the_oracle_puts_it(shape):
+    ny, nx, N = shape
+    tw = case_twin(ny, nx, N, "scalar")
+    c_ref = oracle_c_hat(tw, "matmul")
+    assert (c_ref / c_ref.mean()).min() >= 1e-5
+    x_ref = learned.features(c_ref, nx)
+    for j in range(26):
+        _, lam, mu = gpu_spectrum(tw, one_hot_weights(j))
+        y_gpu = np.log(lam / mu)
+        y_ref = learned.round_bf16(x_ref[:, :, j]).astype(np.float64)
+        bound = 2.0 ** -7 * np.abs(x_ref[:, :, j]) + 1e-3
+        assert np.all(np.abs(y_gpu - y_ref) <= bound), f"feature {j}"
+        assert np.mean(np.abs(y_gpu - y_ref) <= 1e-5) >= 0.98, f"feature {j}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}-N{c[2]}")
+def test_learned_spectrum_matches_oracle(case):
+    ny, nx = case[:2]
+    tw = case_twin(*case)
+    w = random_weights(11 + ny)
+    _, lam_gpu, mu_gpu = gpu_spectrum(tw, w)
+    lam_ref, mu_ref = learned.learned_spectrum(oracle_c_hat(tw, method_for(ny, nx)), nx, w)
+    dy = np.abs(np.log(lam_gpu / mu_gpu) - np.log(lam_ref / mu_ref))
+    assert np.percentile(dy, 99) <= 1e-2
+    assert dy.max() <= 0.1
+    assert rel_l2(lam_gpu, lam_ref) <= 5e-3
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}-N{c[2]}")
+def test_learned_analysis_matches_oracle(case):
+    ny, nx = case[:2]
+    tw = case_twin(*case)
+    w = random_weights(23 + nx)
+    out = _lib.analyze_learned(to_dev(tw.ens), to_dev(tw.data), to_dev(tw.R_spec), tw.seed, _lib.mlp_weights(w, DEV))
+    torch.cuda.synchronize()
+    ref = learned.analyze_learned(tw.ens, tw.data, tw.R_spec, tw.seed, w, method=method_for(ny, nx))
+    assert rel_l2(out.cpu().numpy(), ref) <= 2e-4
+
+
+def test_learned_full_size_2048_n5():
+    """The learned configuration's own size: 2048 x 2048, N = 5, power-law spectrum."""
+    tw = twin.make_twin(2048, 2048, 5, seed=41, dtype=np.float32, kind="power", kw={"a": 3.0}, r=0.05)
+    w = random_weights(5)
+    c_gpu, lam_gpu, mu_gpu = gpu_spectrum(tw, w)
+    c_ref = oracle_c_hat(tw, "fft")
+    assert rel_l2(c_gpu, c_ref) <= 1e-5
+    lam_ref, mu_ref = learned.learned_spectrum(c_ref, 2048, w)
+    dy = np.abs(np.log(lam_gpu / mu_gpu) - np.log(lam_ref / mu_ref))
+    assert np.percentile(dy, 99) <= 1e-2 and dy.max() <= 0.1
+    out = _lib.analyze_learned(to_dev(tw.ens), to_dev(tw.data), to_dev(tw.R_spec), tw.seed, _lib.mlp_weights(w, DEV))
+    torch.cuda.synchronize()
+    ref = learned.analyze_learned(tw.ens, tw.data, tw.R_spec, tw.seed, w, method="fft")
+    assert rel_l2(out.cpu().numpy(), ref) <= 2e-4
+
+
+def test_learned_is_deterministic_and_in_place():
+    tw = case_twin(64, 64, 5, "scalar")
+    wd = _lib.mlp_weights(random_weights(3), DEV)
+    a = _lib.analyze_learned(to_dev(tw.ens), to_dev(tw.data), 0.05, tw.seed, wd)
+    b = _lib.analyze_learned(to_dev(tw.ens), to_dev(tw.data), 0.05, tw.seed, wd)
+    ens = to_dev(tw.ens)
+    c = _lib.analyze_learned(ens, to_dev(tw.data), 0.05, tw.seed, wd, out=ens)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_plain_analysis_unchanged_after_learned_calls():
+    """The learned path's extra sweep modes leave the plain entry point's results alone."""
+    tw = case_twin(128, 64, 5, "spectral")
+    plain0 = _lib.analyze(to_dev(tw.ens), to_dev(tw.data), to_dev(tw.R_spec), tw.seed)
+    _lib.analyze_learned(to_dev(tw.ens), to_dev(tw.data), to_dev(tw.R_spec), tw.seed,
+                         _lib.mlp_weights(random_weights(2), DEV))
+    plain1 = _lib.analyze(to_dev(tw.ens), to_dev(tw.data), to_dev(tw.R_spec), tw.seed)
+    torch.cuda.synchronize()
+    assert torch.equal(plain0, plain1)
