@@ -114,8 +114,12 @@ def spectral_gain(c_hat: np.ndarray, R_spec: np.ndarray, tiny: float) -> np.ndar
 
 
 def analyze_spectral(ens, data, R_spec, e_hat, *, method: str = "matmul", tiny=None,
-                     return_parts: bool = False):
-    """O1 with given spectral perturbations e_hat[N, ny, nx//2+1] (unitary scale)."""
+                     return_parts: bool = False, lam=None):
+    """O1 with given spectral perturbations e_hat[N, ny, nx//2+1] (unitary scale).
+
+    lam, if given, is a prescribed covariance spectrum [ny, nx//2+1] used in the
+    gain of eq. (3) in place of the estimate of eq. (2) (the filter with the
+    known covariance of a twin experiment)."""
     ens = np.asarray(ens)
     N, ny, nx = ens.shape
     if tiny is None:
@@ -124,7 +128,8 @@ def analyze_spectral(ens, data, R_spec, e_hat, *, method: str = "matmul", tiny=N
     u_hat = dft.rdft2(ens.astype(np.float64), method=method)          # step 1
     d_hat = dft.rdft2(np.asarray(data, dtype=np.float64), method=method)
     mean, c_hat = spectral_mean_variance(u_hat)                        # eq. (2)
-    K = spectral_gain(c_hat, R_spec, tiny)                             # eq. (3), gain
+    cov = c_hat if lam is None else np.asarray(lam, dtype=np.float64)
+    K = spectral_gain(cov, R_spec, tiny)                               # eq. (3), gain
     ua_hat = u_hat + K[None] * (d_hat[None] + e_hat - u_hat)           # eq. (3), update
     ua = dft.irdft2(ua_hat, nx, method=method)                         # F^-1
     if return_parts:
@@ -133,13 +138,13 @@ def analyze_spectral(ens, data, R_spec, e_hat, *, method: str = "matmul", tiny=N
 
 
 def analyze(ens, data, R_spec, seed: int, *, method: str = "matmul", tiny=None,
-            return_parts: bool = False):
+            return_parts: bool = False, lam=None):
     """O1: the FFT EnKF analysis with the seeded perturbation convention."""
     ens = np.asarray(ens)
     N, ny, nx = ens.shape
     R_spec = np.broadcast_to(np.asarray(R_spec, dtype=np.float64), (ny, nx // 2 + 1))
     e_hat = spectral_perturbations(seed, N, R_spec, nx)
-    return analyze_spectral(ens, data, R_spec, e_hat, method=method, tiny=tiny, return_parts=return_parts)
+    return analyze_spectral(ens, data, R_spec, e_hat, method=method, tiny=tiny, return_parts=return_parts, lam=lam)
 
 
 # --------------------------------------------------------------- O2, dense

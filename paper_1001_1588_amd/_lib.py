@@ -60,6 +60,8 @@ EXPORTS = {
     "fftenkf_profile_events": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
     "fftenkf_analyze_learned": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                                ctypes.POINTER(Mlp), ctypes.c_void_p]),
+    "fftenkf_analyze_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                                ctypes.c_void_p, ctypes.c_void_p]),
     "fftenkf_debug_learned_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.POINTER(Mlp),
                                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
@@ -143,6 +145,23 @@ def analyze(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, f
     st = lib().fftenkf_analyze(ctypes.byref(e), data.data_ptr(), _ptr(R_t), ctypes.c_uint64(seed & (2**64 - 1)),
                                out.data_ptr())
     _check(st, "fftenkf_analyze")
+    return out
+
+
+def analyze_spectrum(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, float], seed: int,
+                     lam: torch.Tensor, out: Optional[torch.Tensor] = None,
+                     workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Eq. (3) with prescribed covariance eigenvalues lam [ny, nx//2+1] (unitary scale) in place of eq. (2)."""
+    R_t, r = _rspec(R_spec)
+    e, ws = _make_ens(ens, workspace, r)
+    N, ny, nx = ens.shape
+    if tuple(lam.shape) != (ny, nx // 2 + 1) or lam.dtype != ens.dtype or not lam.is_contiguous():
+        raise ValueError("lam must be a contiguous [ny, nx//2+1] tensor of the ensemble's dtype")
+    if out is None:
+        out = torch.empty_like(ens)
+    st = lib().fftenkf_analyze_spectrum(ctypes.byref(e), data.data_ptr(), _ptr(R_t),
+                                        ctypes.c_uint64(seed & (2**64 - 1)), lam.data_ptr(), out.data_ptr())
+    _check(st, "fftenkf_analyze_spectrum")
     return out
 
 

@@ -198,7 +198,7 @@ bool log_enabled() {
 // analysis) K2_UPDATE_LEARNED; mlp_chat/mlp_lam/mlp_mu request the spectra only.
 int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_spec, uint64_t seed, void* out,
         int mode, void* dbg_chat, void* dbg_gain, void* dbg_spec, void* dbg_e, const fftenkf_mlp* mlp = nullptr,
-        void* mlp_chat = nullptr, void* mlp_lam = nullptr, void* mlp_mu = nullptr) {
+        void* mlp_chat = nullptr, void* mlp_lam = nullptr, void* mlp_mu = nullptr, const void* lam = nullptr) {
   if (t_fail_next != 0) {
     const int st = t_fail_next;
     t_fail_next = 0;
@@ -217,7 +217,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
     fprintf(stderr, "fftenkf: N=%d grid %dx%d dtype=%d R=%d L=%d C=%d units=%d group_xcd=%d mode=%d\n", e->n_members,
             e->ny, e->nx, e->dtype, plan.R, plan.L, plan.C, plan.units_total, plan.group_xcd, mode);
 
-  const bool profiled = t_events_on && mode == K2_ANALYZE && mlp == nullptr;
+  const bool profiled = t_events_on && mode == K2_ANALYZE && mlp == nullptr && lam == nullptr;
   if (!profiled) t_events_on = false;
   err = mark(0, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "profile event: %s", hipGetErrorString(err));
@@ -247,6 +247,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   a2.dbg_gain = dbg_gain;
   a2.dbg_spec = dbg_spec;
   a2.dbg_e = dbg_e;
+  a2.lam_map = lam;
   a2.tab = tab;
   if (mlp != nullptr) {
     // the perceptron needs c_hat of every bin, and their mean, before any update
@@ -306,7 +307,7 @@ int check_mlp(const fftenkf_mlp* m, bool device) {
 }
 
 int analyze_impl(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed, const fftenkf_mlp* mlp,
-                 void* out) {
+                 const void* lam, void* out) {
   try {
     Plan plan;
     int st = validate_shape(e, &plan);
@@ -321,12 +322,14 @@ int analyze_impl(const fftenkf_ens* e, const void* data, const void* R_spec, uin
     const size_t field = (size_t)e->ny * e->nx * s;
     const size_t ens_b = field * e->n_members;
     const size_t rs_b = (size_t)e->ny * (e->nx / 2 + 1) * s;
+    if (lam != nullptr && misaligned(lam, 16)) return fail(FFTENKF_EINVAL, "lam must be 16-byte aligned");
     const Ptr ptrs[] = {{e->members, ens_b, "members"},
                         {data, field, "data"},
                         {R_spec, rs_b, "R_spec"},
                         {out, ens_b, "out"},
-                        {e->workspace, plan.ws_bytes, "workspace"}};
-    const int np = 5;
+                        {e->workspace, plan.ws_bytes, "workspace"},
+                        {lam, rs_b, "lam"}};
+    const int np = 6;
     for (int i = 0; i < np; ++i)
       for (int j = i + 1; j < np; ++j) {
         if (ptrs[i].p == nullptr || ptrs[j].p == nullptr) continue;
@@ -341,7 +344,8 @@ int analyze_impl(const fftenkf_ens* e, const void* data, const void* R_spec, uin
     st = check_pointers(ptrs, np);
     if (st == FFTENKF_OK && mlp != nullptr) st = check_mlp(mlp, true);
     if (st != FFTENKF_OK) return st;
-    return run(e, plan, data, R_spec, seed, out, K2_ANALYZE, nullptr, nullptr, nullptr, nullptr, mlp);
+    return run(e, plan, data, R_spec, seed, out, K2_ANALYZE, nullptr, nullptr, nullptr, nullptr, mlp, nullptr, nullptr,
+               nullptr, lam);
   } catch (...) {
     return fail(FFTENKF_EDEVICE, "internal error");
   }
@@ -396,14 +400,20 @@ int fftenkf_profile_events(void* const* events, int n) {
 }
 
 int fftenkf_analyze(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed, void* out) {
-  return analyze_impl(e, data, R_spec, seed, nullptr, out);
+  return analyze_impl(e, data, R_spec, seed, nullptr, nullptr, out);
+}
+
+int fftenkf_analyze_spectrum(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed, const void* lam,
+                             void* out) {
+  if (lam == nullptr) return fail(FFTENKF_EINVAL, "lam is NULL");
+  return analyze_impl(e, data, R_spec, seed, nullptr, lam, out);
 }
 
 int fftenkf_analyze_learned(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed,
                             const fftenkf_mlp* mlp, void* out) {
   if (mlp == nullptr) return fail(FFTENKF_EINVAL, "mlp is NULL");
   if (e != nullptr && e->dtype != FFTENKF_F32) return fail(FFTENKF_EUNSUPPORTED, "the learned covariance is float32 only");
-  return analyze_impl(e, data, R_spec, seed, mlp, out);
+  return analyze_impl(e, data, R_spec, seed, mlp, nullptr, out);
 }
 
 int fftenkf_debug_spectra(const fftenkf_ens* e, const void* data, const void* R_spec, void* c_hat, void* gain,

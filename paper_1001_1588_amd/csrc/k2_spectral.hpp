@@ -174,7 +174,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
         var += d.re * d.re + d.im * d.im;
       }
     T chat = var * var_scale;
-    if (transformed && valid_w) chat = static_cast<const T*>(a.lam_map)[(size_t)ky[i] * nh + kx];
+    if (a.lam_map != nullptr && valid_w) chat = static_cast<const T*>(a.lam_map)[(size_t)ky[i] * nh + kx];
     T rb = T(a.r_scalar);
     if (Rspec != nullptr && valid_w) rb = Rspec[(size_t)ky[i] * nh + kx];
     const T den = chat + rb;

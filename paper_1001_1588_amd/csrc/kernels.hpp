@@ -33,8 +33,9 @@ struct K1Args {
 // K2_STATS: forward transforms and eq. (2) only -- writes c_hat to chat_map,
 //   one partial sum of c_hat per block to partials, and the transformed fields
 //   back in place.
-// K2_UPDATE_LEARNED: starts from those transformed fields and takes the gain
-//   from lam_map (an estimate of the eigenvalues) instead of eq. (2).
+// K2_UPDATE_LEARNED: starts from those transformed fields.
+// In any mode a non-null lam_map replaces eq. (2) in the gain: the covariance
+// eigenvalues are read from it (an estimate, or a prescribed spectrum).
 enum K2Mode { K2_ANALYZE = 0, K2_DEBUG_SPECTRA = 1, K2_DEBUG_PERTURB = 2, K2_STATS = 3, K2_UPDATE_LEARNED = 4 };
 
 struct K2Args {
@@ -52,7 +53,7 @@ struct K2Args {
   void* dbg_e;     // [N][ny][nx/2+1] complex
   void* chat_map;  // [ny][nx/2+1] real (K2_STATS)
   void* partials;  // [units_total] float (K2_STATS)
-  const void* lam_map;  // [ny][nx/2+1] real (K2_UPDATE_LEARNED)
+  const void* lam_map;  // [ny][nx/2+1] real, or nullptr
   const void* tab;
 };
 

@@ -19,6 +19,14 @@ WRF-Fire ideal problem, Section 4):
   lambda(0) = 0, d = truth + N(0, 0.05 I), R = 0.05 I.
 
 In both, members = truth + independent draws from the same field law.
+
+``about="centre"`` builds the twin the way the paper's experiment does
+(Section 4: ensemble and data both made by random perturbation of one state):
+a centre field u, members u + r_k and truth u + r_0 with r_0, r_k independent
+draws of the same law, so the truth is exchangeable with the members and the
+forecast mean's error has spectrum lambda (1 + 1/N).  With the default
+``about="truth"`` the forecast mean sits on the truth, its error spectrum is
+lambda / N, and the spread overstates it N-fold.
 """
 
 from __future__ import annotations
@@ -88,15 +96,22 @@ WORKLOADS = {
 
 
 def make_twin(ny: int, nx: int, N: int, *, seed: int, dtype=np.float32, kind: str = "matern2",
-              kw: Optional[dict] = None, r: float = 0.01, name: str = "") -> Twin:
+              kw: Optional[dict] = None, r: float = 0.01, name: str = "", about: str = "truth") -> Twin:
     """Twin experiment from one master seed (numpy SeedSequence spawned four ways:
-    truth, member draws, data noise, analysis seed)."""
+    truth, member draws, data noise, analysis seed; a fifth, the truth's own
+    draw, when about="centre")."""
     kw = kw or {}
     ss = np.random.SeedSequence(seed)
     s_truth, s_mem, s_obs, s_an = ss.spawn(4)
     lam = spectrum(ny, nx, kind, **kw)
-    truth = gaussian_fields(np.random.default_rng(s_truth), lam, 1)[0]
-    ens = truth[None] + gaussian_fields(np.random.default_rng(s_mem), lam, N)
+    centre = gaussian_fields(np.random.default_rng(s_truth), lam, 1)[0]
+    ens = centre[None] + gaussian_fields(np.random.default_rng(s_mem), lam, N)
+    if about == "truth":
+        truth = centre
+    elif about == "centre":
+        truth = centre + gaussian_fields(np.random.default_rng(ss.spawn(1)[0]), lam, 1)[0]
+    else:
+        raise ValueError(f"about must be 'truth' or 'centre', not {about!r}")
     data = truth + np.sqrt(r) * np.random.default_rng(s_obs).standard_normal((ny, nx))
     an_seed = int(np.random.default_rng(s_an).integers(0, 2**63 - 1, dtype=np.int64))
     R_spec = np.full((ny, nx // 2 + 1), r, dtype=np.float64)

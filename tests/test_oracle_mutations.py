@@ -35,6 +35,7 @@ MUTANTS = [
     ("philox.py", "hi1 ^ x[1] ^ k0, lo1, hi0 ^ x[3] ^ k1", "hi1 ^ x[1] ^ k1, lo1, hi0 ^ x[3] ^ k0"),
     ("philox.py", "np.sqrt(-2.0 * np.log(u1))", "np.sqrt(-1.0 * np.log(u1))"),
     ("philox.py", "ang = 2.0 * np.pi * u2", "ang = np.pi * u2"),
+    ("enkf.py", "cov = c_hat if lam is None else np.asarray(lam, dtype=np.float64)", "cov = c_hat"),
     ("learned.py", "full[:, kx] = c_half[ky, nx - kx]", "full[:, kx] = c_half[:, nx - kx]"),
     ("learned.py", "dy, dx = j // 5 - 2, j % 5 - 2", "dx, dy = j // 5 - 2, j % 5 - 2"),
     ("learned.py", "np.log(full / mu + EPS)", "np.log(full + EPS)"),

@@ -127,3 +127,29 @@ def test_fft_and_matmul_oracles_agree():
     a = enkf.analyze(tw.ens, tw.data, tw.R_spec, tw.seed)
     b = enkf.analyze(tw.ens, tw.data, tw.R_spec, tw.seed, method="fft")
     assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-13
+
+
+def test_prescribed_spectrum_single_mode():
+    """A prescribed flat spectrum lam0 gives the scalar gain lam0 / (lam0 + r) on the mode."""
+    ens, data, a, delta, mode, base = _mode_case(seed=3)
+    N, ny, nx = ens.shape
+    r, lam0 = 0.4, 2.5
+    zero = np.zeros((N, ny, nx // 2 + 1), dtype=complex)
+    out = enkf.analyze_spectral(ens, data, r, zero, lam=np.full((ny, nx // 2 + 1), lam0))
+    K = lam0 / (lam0 + r)
+    expect = base[None] + (a + K * (delta - a))[:, None, None] * mode[None]
+    assert np.allclose(out, expect, atol=1e-12)
+
+
+@pytest.mark.parametrize("ny,nx,N", [(8, 8, 3), (16, 8, 4)])
+def test_prescribed_spectrum_equals_dense_known_covariance(ny, nx, N):
+    """Eq. (1) with the stationary covariance whose eigenvalues are lam, solved densely."""
+    tw = twin.random_ensemble(ny, nx, N, seed=40 + ny, dtype=np.float64, r=0.05, R_kind="spectral")
+    ky = twin.integer_wavenumbers(ny)[:, None]
+    kx = np.arange(nx // 2 + 1)[None, :].astype(np.float64)
+    lam = 1.0 / (1.0 + ky * ky + kx * kx)
+    e_hat = enkf.spectral_perturbations(tw.seed, N, tw.R_spec, nx)
+    o1 = enkf.analyze_spectral(tw.ens, tw.data, tw.R_spec, e_hat, lam=lam)
+    o2 = enkf.analyze_dense(tw.ens, tw.data, enkf.stationary_matrix(tw.R_spec, nx),
+                            enkf.physical_perturbations(e_hat, nx), enkf.stationary_matrix(lam, nx))
+    assert np.linalg.norm(o1 - o2) / np.linalg.norm(o2) < 1e-10
