@@ -121,6 +121,13 @@ typedef struct fftenkf_mlp {
 int fftenkf_analyze_learned(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed,
                             const fftenkf_mlp* mlp, void* out);
 
+/* As fftenkf_analyze, with the covariance eigenvalues prescribed: lam is a
+ * device [ny][nx/2+1] array of dtype (unitary DFT scale, the same scale as
+ * R_spec) used in eq. (3) in place of the estimate of eq. (2), e.g. the known
+ * spectrum of a twin experiment.  Same arguments and error behaviour. */
+int fftenkf_analyze_spectrum(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed,
+                             const void* lam, void* out);
+
 /* Largest N the analysis supports for a dtype. */
 int fftenkf_max_members(int dtype);
 

@@ -182,3 +182,17 @@ def test_trained_weights_beat_plain_rmse_at_n5():
         assert r["learned"] < r["plain"], r
         assert r["learned"] <= 1.01 * r["known"], r
         assert r["plain"] < r["forecast"], r
+
+
+@pytest.mark.parametrize("case", [(16, 16, 4, "spectral"), (256, 64, 5, "scalar"), (64, 512, 20, "spectral")],
+                         ids=lambda c: f"{c[0]}x{c[1]}-N{c[2]}")
+def test_prescribed_spectrum_analysis_matches_oracle(case):
+    """fftenkf_analyze_spectrum: eq. (3) with the generating spectrum in the gain, at the plain path's bar."""
+    ny, nx = case[:2]
+    tw = case_twin(*case)
+    lam = np.ascontiguousarray(tw.lam[:, : nx // 2 + 1])
+    out = _lib.analyze_spectrum(to_dev(tw.ens), to_dev(tw.data), to_dev(tw.R_spec), tw.seed,
+                                to_dev(lam.astype(np.float32)))
+    torch.cuda.synchronize()
+    ref = enkf.analyze(tw.ens, tw.data, tw.R_spec, tw.seed, method=method_for(ny, nx), lam=lam.astype(np.float32))
+    assert rel_l2(out.cpu().numpy(), ref) <= 1e-5
