@@ -8,7 +8,10 @@ with all inputs resident in HBM before the timed region.
 
 Prints one JSON line: member-gridpoints analysed per second, the roofline of the
 dominant sweep (its algorithmic bytes per launch over its average HIP-event
-duration, against 8 TB/s), and the float64 CPU oracle timed on the host.
+duration, against 8 TB/s), and the float64 CPU oracle timed on the host.  A
+second leg times the learned spectral covariance at 2048 x 2048, N = 5 (and the
+plain analysis at the same size), with the perceptron's matrix-core rate and the
+analysis RMSE of the plain, learned and exact-covariance filters.
 """
 
 from __future__ import annotations
@@ -127,6 +130,69 @@ def cpu_baseline(tw, members: int) -> dict:
                       f"{members} of the {tw.ens.shape[0]} members plus d, one analysis, {dt:.1f} s"}
 
 
+MLP_FLOPS_PER_BIN = 2 * (26 * 64 + 64 * 64 + 64 * 64 + 64)  # multiply-adds of the perceptron, x2
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix cores, published
+
+
+def learned_leg(args, hip, dev) -> dict:
+    """The learned spectral covariance at its own configuration (2048 x 2048,
+    N = 5, float32, |k|^-3, R = 0.05 I): time per analysis and per launch, the
+    same analysis with the plain estimate, and the analysis RMSE of the plain,
+    learned and exact-covariance filters on held-out twins."""
+    import torch
+
+    from paper_1001_1588_amd import _lib, evaluate, twin
+
+    w = evaluate.load_weights()
+    wd = _lib.mlp_weights(w, dev)
+    tw = twin.make_twin(2048, 2048, 5, seed=args.seed + 5, dtype=np.float32, kind="power", kw={"a": 3.0},
+                        r=0.05, about="centre")
+    N, ny, nx = tw.ens.shape
+    ens = torch.from_numpy(tw.ens).to(dev)
+    data = torch.from_numpy(tw.data).to(dev)
+    R = torch.from_numpy(tw.R_spec).to(dev)
+    ws = torch.empty(_lib.workspace_bytes(N, ny, nx, torch.float32), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(ens)
+    res = {}
+    for name, nev in (("learned", 6), ("plain", 4)):
+        call = (lambda s: _lib.analyze_learned(ens, data, R, tw.seed + s, wd, out=out, workspace=ws)) \
+            if name == "learned" else (lambda s: _lib.analyze(ens, data, R, tw.seed + s, out=out, workspace=ws))
+        for s in range(args.warmup):
+            call(s)
+        torch.cuda.synchronize()
+        evs = [[hip.create() for _ in range(nev)] for _ in range(args.learned_steps)]
+        t0 = time.perf_counter()
+        for s in range(args.learned_steps):
+            _lib.profile_events(evs[s])
+            call(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = np.array([[hip.elapsed_ms(e[i], e[i + 1]) for i in range(nev - 1)] for e in evs]).mean(axis=0)
+        for e in evs:
+            for x in e:
+                hip.destroy(x)
+        res[name] = {"ms_per_step": 1e3 * wall / args.learned_steps,
+                     "value": N * ny * nx * args.learned_steps / wall, "launch_ms": [float(v) for v in per]}
+    k7_ms = res["learned"]["launch_ms"][2]
+    flops = MLP_FLOPS_PER_BIN * ny * (nx // 2 + 1)
+    rows = evaluate.rmse_study(seeds=[args.seed + 9000], a_values=[2.0, 3.0, 4.0], weights=w, device=dev)
+    mean = {k: float(np.mean([r[k] for r in rows])) for k in ("forecast", "plain", "learned", "known")}
+    return {
+        "workload": "2048x2048 grid, N=5 members, float32, spectrum |k|^-3, R=0.05 I (R_spec array)",
+        "unit": "member-gridpoints/s",
+        "learned": res["learned"] | {"launches": ["sweep1", "sweep2_statistics", "perceptron", "sweep2_update",
+                                                  "sweep3"]},
+        "plain": res["plain"] | {"launches": ["sweep1", "sweep2", "sweep3"]},
+        "perceptron": {"bound": "mfma", "dtype": "bf16", "flops": flops, "ms": k7_ms,
+                       "achieved": flops / (k7_ms * 1e-3) / 1e12, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": flops / (k7_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS},
+        "rmse": {"metric": "RMSE of the analysis ensemble mean vs truth", "mean": mean, "cases": rows,
+                 "twins": "held-out seeds, 2048x2048, N=5, |k|^-a, a in {2,3,4}, R=0.05 I, truth exchangeable "
+                          "with the members"},
+        "weights": json.loads(w["meta"]) if w["meta"] else None,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +202,8 @@ def main() -> int:
     ap.add_argument("--cpu-members", type=int, default=20, help="members in the CPU oracle sample (0 = skip)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the device copy ceiling probe (0 = skip)")
+    ap.add_argument("--learned-steps", type=int, default=20,
+                    help="timed analyses of the learned-covariance leg at N=5 (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -216,6 +284,8 @@ def main() -> int:
     }
     if args.copy_mib > 0:
         result["copy_ceiling"] = copy_ceiling(args.copy_mib, hip)
+    if args.learned_steps > 0:
+        result["learned_covariance"] = learned_leg(args, hip, dev)
     if args.cpu_members > 0:
         result["cpu_baseline"] = cpu_baseline(tw, min(args.cpu_members, N))
     print(json.dumps(result), flush=True)

@@ -160,11 +160,15 @@ int fftenkf_debug_learned_spectrum(const fftenkf_ens* ens, const void* data, con
                                    void* lam_hat, void* mu);
 
 /*
- * Profiling hook for the calling thread: with n == 4, the next fftenkf_analyze
- * records events[0] before sweep 1, events[1] between sweeps 1 and 2, events[2]
- * between sweeps 2 and 3 and events[3] after sweep 3, on ens->stream (each a
- * hipEvent_t created by the caller), then forgets them.  n == 0 clears it.
- * Returns FFTENKF_EINVAL for any other n or a NULL array.
+ * Profiling hook for the calling thread.  With n == 4, the next
+ * fftenkf_analyze or fftenkf_analyze_spectrum records events[0] before sweep 1,
+ * events[1] between sweeps 1 and 2, events[2] between sweeps 2 and 3 and
+ * events[3] after sweep 3.  With n == 6, the next fftenkf_analyze_learned
+ * records them around its five launches (sweep 1, the statistics sweep, the
+ * perceptron, the update sweep, sweep 3).  Events are hipEvent_t created by the
+ * caller, recorded on ens->stream; the hook is forgotten after that call (or
+ * after any call it does not fit).  n == 0 clears it.  Returns FFTENKF_EINVAL
+ * for any other n or a NULL array.
  */
 int fftenkf_profile_events(void* const* events, int n);
 

@@ -57,7 +57,8 @@ namespace {
 
 thread_local std::string t_last_error;
 thread_local int t_fail_next = 0;
-thread_local hipEvent_t t_events[4] = {nullptr, nullptr, nullptr, nullptr};
+thread_local hipEvent_t t_events[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+thread_local int t_nevents = 0;
 thread_local bool t_events_on = false;
 
 hipError_t mark(int i, hipStream_t s) {
@@ -217,7 +218,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
     fprintf(stderr, "fftenkf: N=%d grid %dx%d dtype=%d R=%d L=%d C=%d units=%d group_xcd=%d mode=%d\n", e->n_members,
             e->ny, e->nx, e->dtype, plan.R, plan.L, plan.C, plan.units_total, plan.group_xcd, mode);
 
-  const bool profiled = t_events_on && mode == K2_ANALYZE && mlp == nullptr && lam == nullptr;
+  const bool profiled = t_events_on && mode == K2_ANALYZE && t_nevents == (mlp != nullptr ? 6 : 4);
   if (!profiled) t_events_on = false;
   err = mark(0, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "profile event: %s", hipGetErrorString(err));
@@ -255,6 +256,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
     a2.chat_map = mlp_chat != nullptr ? mlp_chat : ws + plan.off_chat;
     a2.partials = ws + plan.off_part;
     err = launch_k2_f32(a2, stream);
+    if (err == hipSuccess) err = mark(2, stream);
     if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 2 (statistics) launch: %s", hipGetErrorString(err));
     K7Args a7{};
     a7.chat = static_cast<const float*>(a2.chat_map);
@@ -273,21 +275,23 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
     a7.lam = static_cast<float*>(mlp_lam != nullptr ? mlp_lam : ws + plan.off_lam);
     a7.mu_out = static_cast<float*>(mlp_mu);
     err = launch_k7(a7, stream);
+    if (err == hipSuccess) err = mark(3, stream);
     if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "perceptron launch: %s", hipGetErrorString(err));
     if (mode != K2_ANALYZE) return FFTENKF_OK;
     a2.mode = K2_UPDATE_LEARNED;
     a2.lam_map = a7.lam;
     err = launch_k2_f32(a2, stream);
+    if (err == hipSuccess) err = mark(4, stream);
   } else {
     err = e->dtype == FFTENKF_F32 ? launch_k2_f32(a2, stream) : launch_k2_f64(a2, stream);
   }
-  if (err == hipSuccess) err = mark(2, stream);
+  if (err == hipSuccess && mlp == nullptr) err = mark(2, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 2 launch: %s", hipGetErrorString(err));
   if (mode != K2_ANALYZE) return FFTENKF_OK;
 
   K3Args a3{ws_main, ws_nyq, e->n_members, e->ny, e->nx, plan.R, plan.L, out, tab};
   err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
-  if (err == hipSuccess) err = mark(3, stream);
+  if (err == hipSuccess) err = mark(mlp != nullptr ? 5 : 3, stream);
   t_events_on = false;
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 3 launch: %s", hipGetErrorString(err));
   return FFTENKF_OK;
@@ -390,11 +394,12 @@ int fftenkf_profile_events(void* const* events, int n) {
     t_events_on = false;
     return FFTENKF_OK;
   }
-  if (n != 4 || events == nullptr) return fail(FFTENKF_EINVAL, "profile events: need an array of 4 events");
-  for (int i = 0; i < 4; ++i) {
+  if ((n != 4 && n != 6) || events == nullptr) return fail(FFTENKF_EINVAL, "profile events: need an array of 4 or 6 events");
+  for (int i = 0; i < n; ++i) {
     if (events[i] == nullptr) return fail(FFTENKF_EINVAL, "profile events: event %d is NULL", i);
     t_events[i] = static_cast<hipEvent_t>(events[i]);
   }
+  t_nevents = n;
   t_events_on = true;
   return FFTENKF_OK;
 }

@@ -48,7 +48,9 @@ struct K2Geom {
   static constexpr size_t lds_bytes() { return 2 * (size_t)FB * seqp<L>() * sizeof(V2<T>); }
 };
 
-template <typename T, int L, int NMAX>
+// SPLIT compiles the two halves of the learned-covariance analysis (K2_STATS,
+// K2_UPDATE_LEARNED); the single-pass modes are compiled without them.
+template <typename T, int L, int NMAX, bool SPLIT>
 __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args a) {
   constexpr int P = k2_points(L);
   constexpr int TF2 = L / P;
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   }
 
   // forward length-L transforms (the learned update starts from transformed fields)
-  const bool transformed = a.mode == K2_UPDATE_LEARNED;
+  const bool transformed = SPLIT && a.mode == K2_UPDATE_LEARNED;
   if (!transformed) {
 #pragma unroll
   for (int f0 = 0; f0 < NMAX; f0 += FB) {
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
     if (Rspec != nullptr && valid_w) rb = Rspec[(size_t)ky[i] * nh + kx];
     const T den = chat + rb;
     gain[i] = den < tiny_normal<T>() ? T(0) : chat / den;
-    if (a.mode == K2_STATS) {
+    if (SPLIT && a.mode == K2_STATS) {
       if (valid_w) static_cast<T*>(a.chat_map)[(size_t)ky[i] * nh + kx] = chat;
       csum += valid_w ? chat : T(0);
     }
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
     }
   }
   if (a.mode == K2_DEBUG_SPECTRA) return;  // no synchronisation follows
-  if (a.mode == K2_STATS) {
+  if (SPLIT && a.mode == K2_STATS) {
     // transformed fields back in place, and this block's sum of c_hat
     if (valid) {
 #pragma unroll
@@ -286,16 +288,28 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   }
 }
 
-template <typename T, int L, int NMAX>
-hipError_t launch_k2_shape(const K2Args& a, hipStream_t st) {
+template <typename T, int L, int NMAX, bool SPLIT>
+hipError_t launch_k2_variant(const K2Args& a, hipStream_t st) {
   constexpr int P = k2_points(L);
   const dim3 grid(a.units_total), block(a.C * (L / P));
   constexpr size_t lds_bytes = K2Geom<T>::template lds_bytes<L>();
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_spectral<T, L, NMAX>),
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_spectral<T, L, NMAX, SPLIT>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k2_spectral<T, L, NMAX>), grid, block, lds_bytes, st, a);
+  hipLaunchKernelGGL((k2_spectral<T, L, NMAX, SPLIT>), grid, block, lds_bytes, st, a);
   return hipGetLastError();
+}
+
+// The learned-covariance modes exist for float32 only.
+template <typename T, int L, int NMAX>
+hipError_t launch_k2_shape(const K2Args& a, hipStream_t st) {
+  const bool split = a.mode == K2_STATS || a.mode == K2_UPDATE_LEARNED;
+  if constexpr (sizeof(T) == 4) {
+    if (split) return launch_k2_variant<T, L, NMAX, true>(a, st);
+  } else {
+    if (split) return hipErrorInvalidValue;
+  }
+  return launch_k2_variant<T, L, NMAX, false>(a, st);
 }
 
 }  // namespace fftenkf

@@ -4,14 +4,24 @@
 // sample spectrum of eq. (2) in the 5 x 5 wavenumber neighbourhood plus
 // log(1 + |k|) (26 features, padded to 32); three hidden layers of 64 with ReLU
 // and one output give y, and lambda_hat = mu exp(y), mu the mean of c_hat over
-// the stored bins.  Features, weights and hidden activations are bfloat16,
-// products accumulate in float32 (v_mfma_f32_16x16x16_bf16).
+// the stored bins.  Features, weights and hidden activations are bfloat16
+// (v_cvt_pk_bf16_f32, round to nearest even), products accumulate in float32
+// (v_mfma_f32_16x16x32_bf16).
 //
-// Each layer is computed transposed, H^T = W^T X^T, with a 16-bin tile as the
-// N dimension: the accumulator of output block m (lane l holds rows
-// 16 m + 4 (l / 16) + j of column l % 16) is exactly the B operand of input
-// block m of the next layer, so activations never leave registers.  The weight
-// matrices W^T are the A operands and stay in registers for the whole kernel.
+// Each layer is computed transposed, H^T = W^T X^T, with 16 bins as the N
+// dimension.  The accumulator of output block m holds, in lane l, hidden units
+// h = 16 m + 4 (l / 16) + r (r < 4) of bin l % 16.  The next layer takes its
+// B operand for K block kb from the accumulators of blocks 2 kb and 2 kb + 1 of
+// the same lane, which puts hidden unit h at K position
+//   kpos(h) = 32 (m / 2) + 8 (l / 16) + 4 (m % 2) + r;
+// the A operand (W^T, held in registers) is loaded in that same K order, so the
+// activations never leave registers and need no exchange between lanes.
+//
+// The grid is persistent: a block loads the weights once and walks tiles of
+// 8 x 32 bins (each wave: two rows, as two pairs of 16-bin tiles).  Each tile's bfloat16 log spectrum, with a 2-bin halo (columns
+// beyond nx/2 taken from the mirror c_hat(-ky, -kx)), goes to one of two LDS
+// buffers; the next tile's c_hat values are loaded into registers while the
+// current tile is computed.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -20,53 +30,89 @@
 
 namespace fftenkf {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kIn = 26;      // features used
-constexpr int kInPad = 32;   // features padded to two 16-wide blocks
-constexpr int kWidth = 64;   // hidden width
-constexpr int kBinsPerWave = 64;
+constexpr int kIn = 26;     // features used
+constexpr int kWidth = 64;  // hidden width
 constexpr int kThreads = 256;
+constexpr int kTY = 8, kTX = 32;             // bins of a block tile (4 waves x 2 rows x 32 columns)
+constexpr int kHY = kTY + 4, kHX = kTX + 4;  // the tile with its halo
+constexpr int kHalo = kHY * kHX;             // 432 <= 2 * kThreads
 constexpr float kEps = 1e-6f;
+constexpr float kLn2 = 0.69314718055994530942f;
+constexpr int kMaxBlocks = 512;  // two resident blocks on each of 256 compute units
+static_assert(kHalo <= 2 * kThreads, "two halo values per thread");
 
-// float32 -> bfloat16, round to nearest, ties to even (finite inputs)
-__device__ __forceinline__ short to_bf16(float x) {
-  uint32_t b = __float_as_uint(x);
-  b += 0x7FFFu + ((b >> 16) & 1u);
-  return (short)(b >> 16);
+__device__ __forceinline__ __bf16 bf(float x) { return (__bf16)x; }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float bf16_to_f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+// natural logarithm by the hardware log2 (arguments here are >= 1e-6, normal)
+__device__ __forceinline__ float ln(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
 
-__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
+// hidden unit held at K position 8 g + e of K block kb by a lane of row group g
+__device__ __forceinline__ int hidden_at(int kb, int g, int e) { return 16 * (2 * kb + (e >> 2)) + 4 * g + (e & 3); }
 
-// c_hat at a full-spectrum position (ky, kx) with 0 <= ky < ny, -2 <= kx <= nx/2 + 2
-__device__ __forceinline__ float chat_full(const float* __restrict__ chat, int ky, int kx, int ny, int nx) {
-  const int nh = nx / 2 + 1;
-  if (kx < 0) kx += nx;
-  if (kx > nx / 2) {  // mirror: c(ky, kx) = c(ny - ky, nx - kx)
-    ky = (ny - ky) & (ny - 1);
-    kx = nx - kx;
+// one hidden layer on two 16-bin tiles: D_m = b + W^T X for the 4 output
+// blocks of each (the accumulators start at the bias; the two tiles' products
+// are issued together so one tile's epilogue overlaps the other's products),
+// rounded to bfloat16, then ReLU, packed as the next layer's B operands.  ReLU
+// acts on the rounded bits as a signed 16-bit maximum with 0: rounding is
+// monotone and keeps the sign, so this equals rounding relu(D).
+template <int KB>
+__device__ __forceinline__ void layer2(const bf16x8 (&A)[4][KB], const bf16x8 (&X0)[KB], const bf16x8 (&X1)[KB],
+                                       const float* bias, int grp, bf16x8 (&H0)[2], bf16x8 (&H1)[2]) {
+  f32x4 D0[4], D1[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    D0[m] = *reinterpret_cast<const f32x4*>(bias + 16 * m + 4 * grp);
+    D1[m] = D0[m];
   }
-  return chat[(size_t)ky * nh + kx];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      D0[m] = mfma(A[m][k], X0[k], D0[m]);
+      D1[m] = mfma(A[m][k], X1[k], D1[m]);
+    }
+  u32x4 w0[2], w1[2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const bf16x2 p0 = __builtin_convertvector((f32x2{D0[m][2 * q], D0[m][2 * q + 1]}), bf16x2);
+      const bf16x2 p1 = __builtin_convertvector((f32x2{D1[m][2 * q], D1[m][2 * q + 1]}), bf16x2);
+      w0[m >> 1][2 * (m & 1) + q] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p0), s16x2(0)));
+      w1[m >> 1][2 * (m & 1) + q] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p1), s16x2(0)));
+    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    H0[i] = __builtin_bit_cast(bf16x8, w0[i]);
+    H1[i] = __builtin_bit_cast(bf16x8, w1[i]);
+  }
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(kThreads) void k7_spectral_mlp(const K7Args a) {
+__global__ __launch_bounds__(kThreads, 2) void k7_spectral_mlp(const K7Args a) {
   __shared__ float red[kThreads];
-  __shared__ float s_bias[3][kWidth];
-  __shared__ float s_w4[kWidth];
+  __shared__ __attribute__((aligned(16))) float s_bias[3][kWidth];
+  __shared__ __bf16 s_x[2][kHalo];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, grp = lane >> 4;  // MFMA column (bin in tile) and row group
   const int ny = a.ny, nx = a.nx, nh = nx / 2 + 1;
   const long total = (long)ny * nh;
+  const float* __restrict__ chat = a.chat;
 
   // mu: every block sums the per-block partials in the same fixed order
   float s = 0.f;
@@ -76,8 +122,6 @@ __global__ __launch_bounds__(kThreads) void k7_spectral_mlp(const K7Args a) {
     s_bias[0][tid] = a.b1[tid];
     s_bias[1][tid] = a.b2[tid];
     s_bias[2][tid] = a.b3[tid];
-    // the output layer multiplies bfloat16 weights
-    s_w4[tid] = bf16_to_f(to_bf16(a.w4[tid]));
   }
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
@@ -89,114 +133,123 @@ __global__ __launch_bounds__(kThreads) void k7_spectral_mlp(const K7Args a) {
   const float inv_mu = 1.f / mu;
   const float b4 = a.b4[0];
 
-  // A operands: W^T fragments.  Fragment (m, k) of a layer: lane holds
-  // W^T[16 m + col][16 k + 4 grp + j] = W[16 k + 4 grp + j][16 m + col].
-  bf16x4 A1[4][2], A2[4][4], A3[4][4];
+  // A operands.  Layer 1: lane holds W1[8 grp + e][16 m + col] (feature f =
+  // 8 grp + e at K position f); layers 2, 3: W[hidden_at(kb, grp, e)][16 m + col].
+  bf16x8 A1[4][1], A2[4][2], A3[4][2], A4[1][2];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int e = 0; e < 8; ++e) {
+      const int f = 8 * grp + e;
+      A1[m][0][e] = bf(f < kIn ? a.W1[f * kWidth + 16 * m + col] : 0.f);
+    }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int in = 16 * k + 4 * grp + j;
-        A1[m][k][j] = in < kIn ? to_bf16(a.W1[in * kWidth + 16 * m + col]) : (short)0;
-      }
+    for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int in = 16 * k + 4 * grp + j;
-        A2[m][k][j] = to_bf16(a.W2[in * kWidth + 16 * m + col]);
-        A3[m][k][j] = to_bf16(a.W3[in * kWidth + 16 * m + col]);
+      for (int e = 0; e < 8; ++e) {
+        const int h = hidden_at(kb, grp, e);
+        A2[m][kb][e] = bf(a.W2[h * kWidth + 16 * m + col]);
+        A3[m][kb][e] = bf(a.W3[h * kWidth + 16 * m + col]);
       }
   }
+  // output layer as one more product: row 0 of A4 is w4 (same K order), rows
+  // 1..15 are zero, so row 0 of the accumulator is y for the 16 bins
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) A4[0][kb][e] = bf(col == 0 ? a.w4[hidden_at(kb, grp, e)] : 0.f);
 
-  const long wave_base = ((long)blockIdx.x * (kThreads / 64) + wave) * kBinsPerWave;
+  // this lane's features f = 8 grp + e: LDS offset and bit masks selecting the
+  // neighbourhood value (f < 25), |k| (f = 25) or zero
+  int foff[8];
+  uint32_t mnb[8], mk[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int f = 8 * grp + e;
+    foff[e] = f < 25 ? (f / 5) * kHX + (f % 5) : 0;
+    mnb[e] = f < 25 ? 0xFFFFu : 0u;
+    mk[e] = f == 25 ? 0xFFFFu : 0u;
+  }
+
+  // the (up to) two halo positions this thread loads for every tile
+  const int hy0 = tid / kHX, hx0 = tid - hy0 * kHX;
+  const bool has1 = tid + kThreads < kHalo;
+  const int hy1 = (tid + kThreads) / kHX, hx1 = (tid + kThreads) - hy1 * kHX;
+  const int ntx = (nh + kTX - 1) / kTX;
+  const int ntiles = (ny / kTY) * ntx;
+  auto halo_index = [&](int tile, int hy, int hx) -> uint32_t {
+    const int ty0 = (tile / ntx) * kTY, tx0 = (tile % ntx) * kTX;
+    int ky = (ty0 + hy - 2) & (ny - 1);
+    int kx = (tx0 + hx - 2) & (nx - 1);
+    if (kx > nx / 2) {  // c_hat is even: c(ky, kx) = c(-ky, -kx)
+      ky = (ny - ky) & (ny - 1);
+      kx = nx - kx;
+    }
+    return (uint32_t)ky * (uint32_t)nh + (uint32_t)kx;
+  };
+
+  int tile = blockIdx.x;
+  float c0 = 0.f, c1 = 0.f;
+  if (tile < ntiles) {
+    c0 = chat[halo_index(tile, hy0, hx0)];
+    if (has1) c1 = chat[halo_index(tile, hy1, hx1)];
+  }
+  for (int buf = 0; tile < ntiles; tile += gridDim.x, buf ^= 1) {
+    __bf16* sx = s_x[buf];
+    sx[tid] = bf(ln(c0 * inv_mu + kEps));
+    if (has1) sx[tid + kThreads] = bf(ln(c1 * inv_mu + kEps));
+    __syncthreads();  // also: every thread is done with the buffer written next
+    const int next = tile + gridDim.x;
+    if (next < ntiles) {  // prefetch, consumed at the top of the next iteration
+      c0 = chat[halo_index(next, hy0, hx0)];
+      if (has1) c1 = chat[halo_index(next, hy1, hx1)];
+    }
+    const int ty0 = (tile / ntx) * kTY, tx0 = (tile % ntx) * kTX;
+
 #pragma unroll 1
-  for (int tile = 0; tile < kBinsPerWave / 16; ++tile) {
-    const long bin = wave_base + tile * 16 + col;
-    const bool live = bin < total;
-    const long b = live ? bin : 0;
-    const int ky = (int)(b / nh), kx = (int)(b - (long)ky * nh);
-
-    // B operand of layer 1: features 16 k + 4 grp + j of this lane's bin
-    bf16x4 X[2];
+    for (int t = 0; t < 2; ++t) {
+      const int row = 2 * wave + t;
+      const int ky = ty0 + row;
+      const int kyw = ky < ny - ky ? ky : ny - ky;
+      bf16x8 X[2][1];
+      int kxs[2];
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+      for (int u = 0; u < 2; ++u) {
+        const int cb = 16 * u;
+        const int kx = tx0 + cb + col;
+        kxs[u] = kx;
+        const float kmag = __builtin_amdgcn_sqrtf((float)kyw * (float)kyw + (float)kx * (float)kx);
+        const uint32_t kbits = __builtin_bit_cast(uint16_t, bf(ln(1.f + kmag)));
+        const uint16_t* xs = reinterpret_cast<const uint16_t*>(sx) + row * kHX + cb + col;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int f = 16 * k + 4 * grp + j;
-        float v = 0.f;
-        if (f < 25) {
-          const int dy = f / 5 - 2, dx = f % 5 - 2;
-          const float c = chat_full(a.chat, (ky + dy + ny) & (ny - 1), kx + dx, ny, nx);
-          v = logf(c * inv_mu + kEps);
-        } else if (f == 25) {
-          const int kyw = ky < ny - ky ? ky : ny - ky;
-          v = log1pf(sqrtf((float)kyw * (float)kyw + (float)kx * (float)kx));
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t v = xs[foff[e]];
+          X[u][0][e] = __builtin_bit_cast(__bf16, (uint16_t)((v & mnb[e]) | (kbits & mk[e])));
         }
-        X[k][j] = to_bf16(v);
       }
-
-    // hidden layers
-    bf16x4 H[4];
-    {
-      f32x4 D[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        D[m] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < 2; ++k) D[m] = mfma(A1[m][k], X[k], D[m]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) H[m][j] = to_bf16(fmaxf(D[m][j] + s_bias[0][16 * m + 4 * grp + j], 0.f));
-      }
+      bf16x8 Ha[2], Hb[2], Ga[2], Gb[2];  // the two tiles' activations
+      layer2<1>(A1, X[0], X[1], s_bias[0], grp, Ha, Hb);
+      layer2<2>(A2, Ha, Hb, s_bias[1], grp, Ga, Gb);
+      layer2<2>(A3, Ga, Gb, s_bias[2], grp, Ha, Hb);
+      // output layer: y = b4 + w4 . h3 in row 0, held by the lanes of row group 0
+      f32x4 Y0 = f32x4{b4, b4, b4, b4}, Y1 = Y0;
+      Y0 = mfma(A4[0][0], Ha[0], Y0);
+      Y1 = mfma(A4[0][0], Hb[0], Y1);
+      Y0 = mfma(A4[0][1], Ha[1], Y0);
+      Y1 = mfma(A4[0][1], Hb[1], Y1);
+      if (grp == 0 && kxs[0] < nh) a.lam[(size_t)ky * nh + kxs[0]] = mu * expf(Y0[0]);
+      if (grp == 0 && kxs[1] < nh) a.lam[(size_t)ky * nh + kxs[1]] = mu * expf(Y1[0]);
     }
-    {
-      f32x4 D[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        D[m] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) D[m] = mfma(A2[m][k], H[k], D[m]);
-      }
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) H[m][j] = to_bf16(fmaxf(D[m][j] + s_bias[1][16 * m + 4 * grp + j], 0.f));
-    }
-    float y;
-    {
-      f32x4 D[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        D[m] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) D[m] = mfma(A3[m][k], H[k], D[m]);
-      }
-      // output layer: this lane's 16 rows, then the four row groups of the column
-      float part = 0.f;
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = 16 * m + 4 * grp + j;
-          const float h = bf16_to_f(to_bf16(fmaxf(D[m][j] + s_bias[2][r], 0.f)));
-          part += s_w4[r] * h;
-        }
-      part += __shfl_xor(part, 16);
-      part += __shfl_xor(part, 32);
-      y = part + b4;
-    }
-    if (live && grp == 0) a.lam[bin] = mu * expf(y);
   }
 }
 
 hipError_t launch_k7(const K7Args& a, hipStream_t s) {
-  const long total = (long)a.ny * (a.nx / 2 + 1);
-  const long per_block = (long)(kThreads / 64) * kBinsPerWave;
-  const dim3 grid((unsigned)((total + per_block - 1) / per_block)), block(kThreads);
+  const int nh = a.nx / 2 + 1;
+  const int ntiles = (a.ny / kTY) * ((nh + kTX - 1) / kTX);
+  const dim3 grid((unsigned)(ntiles < kMaxBlocks ? ntiles : kMaxBlocks)), block(kThreads);
   hipLaunchKernelGGL(k7_spectral_mlp, grid, block, 0, s, a);
   return hipGetLastError();
 }
 
 }  // namespace fftenkf
+

@@ -140,3 +140,13 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError, match="missing"):
         _lib.lib()
+
+
+def test_profile_events_arguments(built_lib):
+    lib = _lib.lib()
+    arr = (ctypes.c_void_p * 6)(*([0x1000] * 6))
+    assert lib.fftenkf_profile_events(arr, 5) == _lib.EINVAL
+    assert lib.fftenkf_profile_events(None, 4) == _lib.EINVAL
+    nulls = (ctypes.c_void_p * 6)()
+    assert lib.fftenkf_profile_events(nulls, 6) == _lib.EINVAL
+    assert lib.fftenkf_profile_events(None, 0) == _lib.OK
