@@ -41,8 +41,12 @@
  *
  * Errors: arguments are validated before anything is enqueued; on any error
  * nothing is written and the return value is negative.  NaN or Inf in the
- * numeric inputs is not checked and propagates.  No C++ exception crosses
- * this interface.  fftenkf_last_error() gives a message for the calling thread.
+ * numeric inputs is not checked and propagates, unless the environment
+ * variable FFTENKF_CHECK is "1": then the analysis entry points first wait
+ * for ens->stream, copy R_spec (and a prescribed lam) to the host and return
+ * FFTENKF_EINVAL if any entry is negative, NaN or infinite.  No C++ exception
+ * crosses this interface.  fftenkf_last_error() gives a message for the
+ * calling thread.
  *
  * Concurrency: calls are asynchronous on ens->stream, like a kernel launch.
  * Two calls sharing a workspace must be ordered on one stream.
@@ -128,6 +132,11 @@ int fftenkf_analyze_learned(const fftenkf_ens* ens, const void* data, const void
 int fftenkf_analyze_spectrum(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed,
                              const void* lam, void* out);
 
+/* Releases cached library state.  The library keeps only its twiddle tables,
+ * which are static device arrays filled on first use and live until the
+ * process ends, so there is nothing to free: returns FFTENKF_OK. */
+int fftenkf_release_caches(void);
+
 /* Largest N the analysis supports for a dtype. */
 int fftenkf_max_members(int dtype);
 
@@ -153,6 +162,16 @@ int fftenkf_debug_spectra(const fftenkf_ens* ens, const void* data, const void* 
 int fftenkf_debug_perturb(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed,
                           void* e_hat);
 void fftenkf_debug_fail_next(int status);
+
+/* Test-only: the 2D transform of the analysis on its own (Section 2.1, step 1
+ * and the inverse F^-1).  inverse == 0: out (device [N][ny][nx/2+1] complex of
+ * dtype) receives the unitary half spectra of ens->members; `spectra` is not
+ * read.  inverse == 1: out (device [N][ny][nx] real) receives the real inverse
+ * of the unitary half spectra in `spectra` ([N][ny][nx/2+1] complex): the real
+ * part of the inverse transform of their Hermitian extension, so the imaginary
+ * parts of the kx = 0 and kx = nx/2 bins act through their Hermitian part
+ * only; ens->members must be non-NULL but is not read.  Uses the workspace. */
+int fftenkf_debug_fft2(const fftenkf_ens* ens, int inverse, const void* spectra, void* out);
 
 /* Test-only: c_hat (eq. (2)) and lambda_hat (the perceptron) per stored bin,
  * device [ny][nx/2+1] float each, and mu (device, one float); float32 only. */

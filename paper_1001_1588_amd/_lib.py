@@ -62,6 +62,8 @@ EXPORTS = {
                                                ctypes.POINTER(Mlp), ctypes.c_void_p]),
     "fftenkf_analyze_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                                 ctypes.c_void_p, ctypes.c_void_p]),
+    "fftenkf_release_caches": (ctypes.c_int, []),
+    "fftenkf_debug_fft2": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "fftenkf_debug_learned_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.POINTER(Mlp),
                                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
@@ -237,6 +239,26 @@ def debug_learned_spectrum(ens: torch.Tensor, data: torch.Tensor, weights: dict)
                                               lam.data_ptr(), mu.data_ptr())
     _check(st, "fftenkf_debug_learned_spectrum")
     return c_hat, lam, mu
+
+
+def debug_rfft2(ens: torch.Tensor) -> torch.Tensor:
+    """Unitary half spectra [N, ny, nx//2+1, 2] of the fields ens [N, ny, nx] (the library's forward transform)."""
+    e, ws = _make_ens(ens, None, 0.0)
+    N, ny, nx = ens.shape
+    out = torch.empty((N, ny, nx // 2 + 1, 2), dtype=ens.dtype, device=ens.device)
+    _check(lib().fftenkf_debug_fft2(ctypes.byref(e), 0, None, out.data_ptr()), "fftenkf_debug_fft2")
+    return out
+
+
+def debug_irfft2(spectra: torch.Tensor, nx: int) -> torch.Tensor:
+    """Real fields [N, ny, nx] from unitary half spectra [N, ny, nx//2+1, 2] (the library's inverse transform)."""
+    if spectra.dim() != 4 or spectra.shape[-1] != 2 or spectra.shape[2] != nx // 2 + 1 or not spectra.is_contiguous():
+        raise ValueError("spectra must be a contiguous [N, ny, nx//2+1, 2] tensor")
+    N, ny = spectra.shape[:2]
+    out = torch.empty((N, ny, nx), dtype=spectra.dtype, device=spectra.device)
+    e, ws = _make_ens(out, None, 0.0)
+    _check(lib().fftenkf_debug_fft2(ctypes.byref(e), 1, spectra.data_ptr(), out.data_ptr()), "fftenkf_debug_fft2")
+    return out
 
 
 def debug_fail_next(status: int) -> None:

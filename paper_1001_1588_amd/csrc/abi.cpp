@@ -8,7 +8,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -297,6 +299,89 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   return FFTENKF_OK;
 }
 
+// Read on every call, so the switch can be flipped while the process runs.
+bool check_enabled() {
+  const char* v = getenv("FFTENKF_CHECK");
+  return v != nullptr && v[0] == '1' && v[1] == '\0';
+}
+
+// With FFTENKF_CHECK=1: every entry of a device array of n reals is finite and >= 0.
+int check_spectrum_values(const void* p, size_t n, int dtype, hipStream_t stream, const char* what) {
+  if (p == nullptr || !check_enabled()) return FFTENKF_OK;
+  hipError_t err = hipStreamSynchronize(stream);
+  std::vector<double> host(n);
+  if (err == hipSuccess) {
+    if (dtype == FFTENKF_F64) {
+      err = hipMemcpy(host.data(), p, n * sizeof(double), hipMemcpyDeviceToHost);
+    } else {
+      std::vector<float> f(n);
+      err = hipMemcpy(f.data(), p, n * sizeof(float), hipMemcpyDeviceToHost);
+      for (size_t i = 0; i < n; ++i) host[i] = f[i];
+    }
+  }
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "%s check: %s", what, hipGetErrorString(err));
+  for (size_t i = 0; i < n; ++i)
+    if (!(host[i] >= 0.0) || !std::isfinite(host[i]))
+      return fail(FFTENKF_EINVAL, "%s[%zu] = %g: entries must be finite and >= 0", what, i, host[i]);
+  return FFTENKF_OK;
+}
+
+// The 2D transform alone: forward (sweep 1, the statistics mode of sweep 2,
+// gather) or inverse (scatter, the inverse-only mode of sweep 2, sweep 3).
+int run_fft2(const fftenkf_ens* e, const Plan& plan, int inverse, const void* spectra, void* out) {
+  if (t_fail_next != 0) {
+    const int st = t_fail_next;
+    t_fail_next = 0;
+    return fail(st, "failure forced by fftenkf_debug_fail_next");
+  }
+  hipStream_t stream = static_cast<hipStream_t>(e->stream);
+  const void* tab = nullptr;
+  hipError_t err = twiddle_table(e->dtype, &tab);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
+  char* ws = static_cast<char*>(e->workspace);
+  void* ws_main = ws;
+  void* ws_nyq = ws + plan.off_nyq;
+  const double n = (double)e->ny * (double)e->nx;
+  K2Args a2{};
+  a2.ws_main = ws_main;
+  a2.ws_nyq = ws_nyq;
+  a2.r_scalar = 1.0;
+  a2.N = e->n_members;
+  a2.ny = e->ny;
+  a2.nx = e->nx;
+  a2.R = plan.R;
+  a2.L = plan.L;
+  a2.C = plan.C;
+  a2.units_main = plan.units_main;
+  a2.units_total = plan.units_total;
+  a2.group_xcd = plan.group_xcd;
+  a2.chat_map = ws + plan.off_chat;
+  a2.partials = ws + plan.off_part;
+  a2.tab = tab;
+  K8Args a8{ws_main, ws_nyq, e->n_members, e->ny, e->nx, plan.R, plan.L, 0.0, nullptr};
+  auto k2 = [&]() { return e->dtype == FFTENKF_F32 ? launch_k2_f32(a2, stream) : launch_k2_f64(a2, stream); };
+  if (!inverse) {
+    // the members double as d: sweep 2 needs a data field, which is not used here
+    K1Args a1{e->members, e->members, e->n_members, e->ny, e->nx, plan.R, plan.L, ws_main, ws_nyq, tab};
+    err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
+    a2.mode = K2_STATS;
+    if (err == hipSuccess) err = k2();
+    a8.scale = 1.0 / std::sqrt(n);
+    a8.spectra = out;
+    if (err == hipSuccess) err = launch_k8_gather(a8, e->dtype, stream);
+  } else {
+    a8.scale = std::sqrt(n);
+    a8.spectra = const_cast<void*>(spectra);
+    err = launch_k8_scatter(a8, e->dtype, stream);
+    a2.mode = K2_INVERSE;
+    if (err == hipSuccess) err = k2();
+    K3Args a3{ws_main, ws_nyq, e->n_members, e->ny, e->nx, plan.R, plan.L, out, tab};
+    if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
+  }
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "transform launch: %s", hipGetErrorString(err));
+  return FFTENKF_OK;
+}
+
 // The eight weight arrays of the perceptron: present and aligned (host-side
 // checks), then device memory of the current device.
 int check_mlp(const fftenkf_mlp* m, bool device) {
@@ -347,6 +432,10 @@ int analyze_impl(const fftenkf_ens* e, const void* data, const void* R_spec, uin
     }
     st = check_pointers(ptrs, np);
     if (st == FFTENKF_OK && mlp != nullptr) st = check_mlp(mlp, true);
+    const size_t plane = (size_t)e->ny * (e->nx / 2 + 1);
+    hipStream_t stream = static_cast<hipStream_t>(e->stream);
+    if (st == FFTENKF_OK) st = check_spectrum_values(R_spec, plane, e->dtype, stream, "R_spec");
+    if (st == FFTENKF_OK) st = check_spectrum_values(lam, plane, e->dtype, stream, "lam");
     if (st != FFTENKF_OK) return st;
     return run(e, plan, data, R_spec, seed, out, K2_ANALYZE, nullptr, nullptr, nullptr, nullptr, mlp, nullptr, nullptr,
                nullptr, lam);
@@ -500,6 +589,36 @@ int fftenkf_debug_learned_spectrum(const fftenkf_ens* e, const void* data, const
     if (st != FFTENKF_OK) return st;
     return run(e, plan, data, nullptr, 0, nullptr, K2_STATS, nullptr, nullptr, nullptr, nullptr, mlp, c_hat, lam_hat,
                mu);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+int fftenkf_release_caches(void) { return FFTENKF_OK; }
+
+int fftenkf_debug_fft2(const fftenkf_ens* e, int inverse, const void* spectra, void* out) {
+  try {
+    Plan plan;
+    int st = validate_shape(e, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (inverse != 0 && inverse != 1) return fail(FFTENKF_EINVAL, "inverse must be 0 or 1");
+    if (out == nullptr || (inverse && spectra == nullptr)) return fail(FFTENKF_EINVAL, "out (and spectra for the inverse) required");
+    if (misaligned(out, 16) || (spectra != nullptr && misaligned(spectra, 16)))
+      return fail(FFTENKF_EINVAL, "spectra and out must be 16-byte aligned");
+    const size_t s = dsize(e->dtype);
+    const size_t fields = (size_t)e->ny * e->nx * s * e->n_members;
+    const size_t specs = (size_t)e->ny * (e->nx / 2 + 1) * 2 * s * e->n_members;
+    const Ptr ptrs[] = {{inverse ? nullptr : e->members, fields, "members"},
+                        {inverse ? spectra : nullptr, specs, "spectra"},
+                        {out, inverse ? fields : specs, "out"},
+                        {e->workspace, plan.ws_bytes, "workspace"}};
+    for (int i = 0; i < 4; ++i)
+      for (int j = i + 1; j < 4; ++j)
+        if (ptrs[i].p && ptrs[j].p && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+    st = check_pointers(ptrs, 4);
+    if (st != FFTENKF_OK) return st;
+    return run_fft2(e, plan, inverse, spectra, out);
   } catch (...) {
     return fail(FFTENKF_EDEVICE, "internal error");
   }

@@ -48,8 +48,9 @@ struct K2Geom {
   static constexpr size_t lds_bytes() { return 2 * (size_t)FB * seqp<L>() * sizeof(V2<T>); }
 };
 
-// SPLIT compiles the two halves of the learned-covariance analysis (K2_STATS,
-// K2_UPDATE_LEARNED); the single-pass modes are compiled without them.
+// SPLIT compiles the modes that start or stop at the transformed fields
+// (K2_STATS, K2_UPDATE_LEARNED, K2_INVERSE); the single-pass modes are compiled
+// without them.
 template <typename T, int L, int NMAX, bool SPLIT>
 __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args a) {
   constexpr int P = k2_points(L);
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   }
 
   // forward length-L transforms (the learned update starts from transformed fields)
-  const bool transformed = SPLIT && a.mode == K2_UPDATE_LEARNED;
+  const bool transformed = SPLIT && (a.mode == K2_UPDATE_LEARNED || a.mode == K2_INVERSE);
   if (!transformed) {
 #pragma unroll
   for (int f0 = 0; f0 < NMAX; f0 += FB) {
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
 
   // ---- perturbations and update, two members per Philox call
   const bool edge = (kx == 0) || (kx == nxh);
-  static_for<0, P>([&](auto I) __attribute__((always_inline)) {
+  if (!(SPLIT && a.mode == K2_INVERSE)) static_for<0, P>([&](auto I) __attribute__((always_inline)) {
     constexpr int i = decltype(I)::value;
     const bool mirrored = edge && ky[i] > (ny >> 1);
     const bool selfconj = edge && (ky[i] == 0 || ky[i] == (ny >> 1));
@@ -300,15 +301,10 @@ hipError_t launch_k2_variant(const K2Args& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The learned-covariance modes exist for float32 only.
 template <typename T, int L, int NMAX>
 hipError_t launch_k2_shape(const K2Args& a, hipStream_t st) {
-  const bool split = a.mode == K2_STATS || a.mode == K2_UPDATE_LEARNED;
-  if constexpr (sizeof(T) == 4) {
-    if (split) return launch_k2_variant<T, L, NMAX, true>(a, st);
-  } else {
-    if (split) return hipErrorInvalidValue;
-  }
+  const bool split = a.mode == K2_STATS || a.mode == K2_UPDATE_LEARNED || a.mode == K2_INVERSE;
+  if (split) return launch_k2_variant<T, L, NMAX, true>(a, st);
   return launch_k2_variant<T, L, NMAX, false>(a, st);
 }
 

@@ -36,7 +36,16 @@ struct K1Args {
 // K2_UPDATE_LEARNED: starts from those transformed fields.
 // In any mode a non-null lam_map replaces eq. (2) in the gain: the covariance
 // eigenvalues are read from it (an estimate, or a prescribed spectrum).
-enum K2Mode { K2_ANALYZE = 0, K2_DEBUG_SPECTRA = 1, K2_DEBUG_PERTURB = 2, K2_STATS = 3, K2_UPDATE_LEARNED = 4 };
+// K2_INVERSE: starts from transformed fields and only applies the inverse
+//   length-L transforms (the c2r test export).
+enum K2Mode {
+  K2_ANALYZE = 0,
+  K2_DEBUG_SPECTRA = 1,
+  K2_DEBUG_PERTURB = 2,
+  K2_STATS = 3,
+  K2_UPDATE_LEARNED = 4,
+  K2_INVERSE = 5
+};
 
 struct K2Args {
   void* ws_main;
@@ -99,6 +108,19 @@ struct K7Args {
   float* mu_out;    // [1] or nullptr
 };
 hipError_t launch_k7(const K7Args& a, hipStream_t s);
+
+// Test exports: move N half spectra ([N][ny][nx/2+1] complex, scaled by
+// `scale`) out of / into the transformed layout the spectral sweep leaves in
+// the workspace (main [f][k2][k1][kx < nx/2], nyq [f][k1][k2], ky = k2 + R k1).
+struct K8Args {
+  void* ws_main;
+  void* ws_nyq;
+  int N, ny, nx, R, L;
+  double scale;
+  void* spectra;
+};
+hipError_t launch_k8_gather(const K8Args& a, int dtype, hipStream_t s);
+hipError_t launch_k8_scatter(const K8Args& a, int dtype, hipStream_t s);
 
 // Device address of the W_4096^k table (float2 for dtype 0, double2 for 1) on
 // the current device, filled from float64 host values on first use.

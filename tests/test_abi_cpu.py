@@ -150,3 +150,14 @@ def test_profile_events_arguments(built_lib):
     nulls = (ctypes.c_void_p * 6)()
     assert lib.fftenkf_profile_events(nulls, 6) == _lib.EINVAL
     assert lib.fftenkf_profile_events(None, 0) == _lib.OK
+
+
+def test_release_caches_and_fft2_arguments(built_lib):
+    lib = _lib.lib()
+    assert lib.fftenkf_release_caches() == _lib.OK
+    e = _ens()
+    assert lib.fftenkf_debug_fft2(ctypes.byref(e), 2, None, 0x300000) == _lib.EINVAL       # direction
+    assert lib.fftenkf_debug_fft2(ctypes.byref(e), 0, None, None) == _lib.EINVAL           # no output
+    assert lib.fftenkf_debug_fft2(ctypes.byref(e), 1, None, 0x300000) == _lib.EINVAL       # inverse needs spectra
+    assert lib.fftenkf_debug_fft2(ctypes.byref(e), 0, None, 0x300008) == _lib.EINVAL       # misaligned
+    assert lib.fftenkf_debug_fft2(ctypes.byref(e), 0, None, 0x100000 + 64) == _lib.EINVAL  # out overlaps members
