@@ -17,6 +17,10 @@ WRF-Fire ideal problem, Section 4):
   d = truth + N(0, 0.01 I), R = 0.01 I.
 * ``large2048`` -- periodic 2048x2048, float32, N=20, lambda = |k|^-3 (k != 0),
   lambda(0) = 0, d = truth + N(0, 0.05 I), R = 0.05 I.
+* multi-block (``make_multiblock_twin``) -- 4 fields of 1024x1024, float32,
+  N=10, lambda_b = (1 + |k|^2 / L_b^2)^-2 with L_b in {8, 16, 32, 64}, spectral
+  coherence 0.6 between blocks through a shared latent field, d observes block
+  0 with R = 0.02 I (Section 2.2).
 
 In both, members = truth + independent draws from the same field law.
 
@@ -138,3 +142,56 @@ def random_ensemble(ny: int, nx: int, N: int, *, seed: int, dtype=np.float32, r:
         R = r * (0.5 + 1.5 / (1.0 + (ky * ky + kx * kx) / 16.0))
         tw.R_spec = R.astype(dtype)
     return tw
+
+
+@dataclasses.dataclass
+class MultiTwin:
+    """Multi-block analysis problem: M fields per member, block 0 observed."""
+
+    ens: np.ndarray        # [N, M, ny, nx] member-major state vectors
+    data: np.ndarray       # [ny, nx], observes block 0
+    R_spec: np.ndarray     # [ny, nx//2 + 1]
+    r: float
+    seed: int
+    truth: np.ndarray      # [M, ny, nx]
+    lam: np.ndarray        # [M, ny, nx] spectra of the blocks
+    rho: float             # spectral coherence between blocks
+
+
+def coherent_fields(rng: np.random.Generator, lams: np.ndarray, rho: float, count: int) -> np.ndarray:
+    """`count` draws of M jointly Gaussian stationary fields [count, M, ny, nx]:
+    block b filters sqrt(rho) w_shared + sqrt(1 - rho) w_b by sqrt(lambda_b), so
+    every pair of blocks has spectral coherence rho at every wavenumber."""
+    M, ny, nx = lams.shape
+    amp = np.sqrt(lams[:, :, : nx // 2 + 1])
+    out = np.empty((count, M, ny, nx), dtype=np.float64)
+    for c in range(count):
+        shared = rng.standard_normal((ny, nx))
+        for b in range(M):
+            w = np.sqrt(rho) * shared + np.sqrt(1.0 - rho) * rng.standard_normal((ny, nx))
+            out[c, b] = np.fft.irfft2(np.fft.rfft2(w, norm="ortho") * amp[b], s=(ny, nx), norm="ortho")
+    return out
+
+
+def make_multiblock_twin(ny: int, nx: int, N: int, *, seed: int, Ls=(8.0, 16.0, 32.0, 64.0), rho: float = 0.6,
+                         r: float = 0.02, dtype=np.float32, about: str = "truth") -> MultiTwin:
+    """Multi-block twin: blocks with spectra (1 + |k|^2 / L_b^2)^-2 (mean 1),
+    coherence rho through a shared latent white noise, members = truth + draws
+    (about="truth") or truth and members both draws about a centre
+    (about="centre"); data = block 0 of the truth + N(0, r I)."""
+    ss = np.random.SeedSequence(seed)
+    s_truth, s_mem, s_obs, s_an = ss.spawn(4)
+    lams = np.stack([spectrum(ny, nx, "matern2", L=L) for L in Ls])
+    centre = coherent_fields(np.random.default_rng(s_truth), lams, rho, 1)[0]
+    ens = centre[None] + coherent_fields(np.random.default_rng(s_mem), lams, rho, N)
+    if about == "truth":
+        truth = centre
+    elif about == "centre":
+        truth = centre + coherent_fields(np.random.default_rng(ss.spawn(1)[0]), lams, rho, 1)[0]
+    else:
+        raise ValueError(f"about must be 'truth' or 'centre', not {about!r}")
+    data = truth[0] + np.sqrt(r) * np.random.default_rng(s_obs).standard_normal((ny, nx))
+    an_seed = int(np.random.default_rng(s_an).integers(0, 2**63 - 1, dtype=np.int64))
+    R_spec = np.full((ny, nx // 2 + 1), r, dtype=np.float64)
+    return MultiTwin(ens=ens.astype(dtype), data=data.astype(dtype), R_spec=R_spec.astype(dtype), r=r,
+                     seed=an_seed, truth=truth.astype(dtype), lam=lams, rho=rho)

@@ -15,7 +15,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["test_oracle_dft.py", "test_oracle_variance.py", "test_oracle_update.py", "test_oracle_rng.py",
-             "test_oracle_learned.py"]
+             "test_oracle_learned.py", "test_oracle_multiblock.py"]
 
 MUTANTS = [
     ("enkf.py", "sum(axis=0) / (N - 1)", "sum(axis=0) / N"),
@@ -36,6 +36,11 @@ MUTANTS = [
     ("philox.py", "np.sqrt(-2.0 * np.log(u1))", "np.sqrt(-1.0 * np.log(u1))"),
     ("philox.py", "ang = 2.0 * np.pi * u2", "ang = np.pi * u2"),
     ("enkf.py", "cov = c_hat if lam is None else np.asarray(lam, dtype=np.float64)", "cov = c_hat"),
+    ("multiblock.py", "(dj * np.conj(d1)).sum(axis=0)", "(np.conj(dj) * d1).sum(axis=0)"),
+    ("multiblock.py", "out_hat[:, j] = u_hat[:, j] + G[None] * innov", "out_hat[:, j] = u_hat[:, 0] + G[None] * innov"),
+    ("multiblock.py", "np.roll(a, (-hy, -hx), axis=(1, 2)) * b", "np.roll(a, (hy, hx), axis=(1, 2)) * b"),
+    ("multiblock.py", "G = np.where(den < tiny, 0.0, cj1 / np.where(den < tiny, 1.0, den))",
+     "G = np.where(den < tiny, 0.0, cj1 / np.where(den < tiny, 1.0, c11))"),
     ("learned.py", "full[:, kx] = c_half[ky, nx - kx]", "full[:, kx] = c_half[:, nx - kx]"),
     ("learned.py", "dy, dx = j // 5 - 2, j % 5 - 2", "dx, dy = j // 5 - 2, j % 5 - 2"),
     ("learned.py", "np.log(full / mu + EPS)", "np.log(full + EPS)"),
