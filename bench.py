@@ -11,7 +11,8 @@ dominant sweep (its algorithmic bytes per launch over its average HIP-event
 duration, against 8 TB/s), and the float64 CPU oracle timed on the host.  A
 second leg times the learned spectral covariance at 2048 x 2048, N = 5 (and the
 plain analysis at the same size), with the perceptron's matrix-core rate and the
-analysis RMSE of the plain, learned and exact-covariance filters.
+analysis RMSE of the plain, learned and exact-covariance filters; a third times
+the multi-block analysis (4 fields of 1024 x 1024, N = 10).
 """
 
 from __future__ import annotations
@@ -193,6 +194,53 @@ def learned_leg(args, hip, dev) -> dict:
     }
 
 
+def multiblock_leg(args, hip, dev) -> dict:
+    """The multi-block analysis at its own configuration: 4 fields of 1024 x 1024,
+    N = 10, float32, coherence 0.6, block 0 observed with R = 0.02 I (R_spec
+    array).  Time per analysis and per sweep, and the multi-block sweep's HBM
+    rate on its algorithmic bytes."""
+    import torch
+
+    from paper_1001_1588_amd import _lib, twin
+
+    tw = twin.make_multiblock_twin(1024, 1024, 10, seed=args.seed + 3, dtype=np.float32)
+    N, M, ny, nx = tw.ens.shape
+    ens = torch.from_numpy(tw.ens).to(dev)
+    data = torch.from_numpy(tw.data).to(dev)
+    R = torch.from_numpy(tw.R_spec).to(dev)
+    ws = torch.empty(int(_lib.lib().fftenkf_workspace_bytes_multi(N, M, ny, nx, 0)), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(ens)
+    for s in range(args.warmup):
+        _lib.analyze_multi(ens, data, R, tw.seed + s, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    steps = args.multi_steps
+    evs = [[hip.create() for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        _lib.profile_events(evs[s])
+        _lib.analyze_multi(ens, data, R, tw.seed + s, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([[hip.elapsed_ms(e[i], e[i + 1]) for i in range(3)] for e in evs]).mean(axis=0)
+    for e in evs:
+        for x in e:
+            hip.destroy(x)
+    b = sweep_bytes(N * M, ny, nx, 4, True)
+    names = ["sweep1", "sweep2_multiblock", "sweep3"]
+    keys = ["sweep1", "sweep2", "sweep3"]
+    return {
+        "workload": "4 fields of 1024x1024, N=10 members, float32, (1+|k|^2/L_b^2)^-2 with L_b in {8,16,32,64}, "
+                    "coherence 0.6, block 0 observed, R=0.02 I (R_spec array)",
+        "unit": "member-gridpoints/s",
+        "value": N * M * ny * nx * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "steps": steps,
+        "sweep_ms": {names[i]: float(per[i]) for i in range(3)},
+        "sweep_hbm_frac": {names[i]: b[keys[i]] / (per[i] * 1e-3) / 1e9 / HBM_PEAK_GBS for i in range(3)},
+        "algorithmic_bytes": {names[i]: b[keys[i]] for i in range(3)},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +250,8 @@ def main() -> int:
     ap.add_argument("--cpu-members", type=int, default=20, help="members in the CPU oracle sample (0 = skip)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the device copy ceiling probe (0 = skip)")
+    ap.add_argument("--multi-steps", type=int, default=20,
+                    help="timed analyses of the multi-block leg (0 = skip)")
     ap.add_argument("--learned-steps", type=int, default=20,
                     help="timed analyses of the learned-covariance leg at N=5 (0 = skip)")
     args = ap.parse_args()
@@ -286,6 +336,8 @@ def main() -> int:
         result["copy_ceiling"] = copy_ceiling(args.copy_mib, hip)
     if args.learned_steps > 0:
         result["learned_covariance"] = learned_leg(args, hip, dev)
+    if args.multi_steps > 0:
+        result["multiblock"] = multiblock_leg(args, hip, dev)
     if args.cpu_members > 0:
         result["cpu_baseline"] = cpu_baseline(tw, min(args.cpu_members, N))
     print(json.dumps(result), flush=True)

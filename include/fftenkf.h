@@ -132,6 +132,34 @@ int fftenkf_analyze_learned(const fftenkf_ens* ens, const void* data, const void
 int fftenkf_analyze_spectrum(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed,
                              const void* lam, void* out);
 
+/*
+ * Multi-block analysis (Section 2.2): every member is a state of M blocks
+ * (fields) on one grid and only block 0 is observed (H = [I 0 .. 0]).  Eq. (5)
+ * in the frequency domain, eq. (6): for every block j and bin
+ *   u_hat^(j)a_k = u_hat^(j)_k + c_hat^(j0) / (c_hat^(00) + R_spec) (d_hat + e_hat_k - u_hat^(0)_k),
+ *   c_hat^(j0) = 1/(N-1) sum_k (u_hat^(j)_k - mean^(j)) conj(u_hat^(0)_k - mean^(0)),
+ * the spectral cross-covariance of eq. (7) with the conjugate on the observed
+ * factor, which makes c_hat^(j0) the eigenvalues of the circulant
+ * (lag-averaged) cross-covariance of block j with block 0; the printed form
+ * conjugates the other factor, which gives their complex conjugates.  Block 0
+ * gets exactly the single-block update of fftenkf_analyze, and e_hat_k follows
+ * the same seeded convention.
+ *   ens->members, out : [N][M][ny][nx]  (member-major state vectors)
+ *   data              : [ny][nx], observes block 0
+ *   R_spec            : [ny][nx/2+1] or NULL (ens->r_scalar), as for fftenkf_analyze
+ *   workspace         : fftenkf_workspace_bytes_multi(N, M, ny, nx, dtype) bytes
+ * 1 <= n_blocks <= 64 and 2 <= N <= fftenkf_max_members_multi(dtype).  Other
+ * rules (alignment, overlap, in place, errors) as for fftenkf_analyze.
+ */
+int fftenkf_analyze_multi(const fftenkf_ens* ens, int n_blocks, const void* data, const void* R_spec, uint64_t seed,
+                          void* out);
+
+/* Workspace bytes of fftenkf_analyze_multi; 0 if the arguments are invalid. */
+size_t fftenkf_workspace_bytes_multi(int n_members, int n_blocks, int ny, int nx, int dtype);
+
+/* Largest N of fftenkf_analyze_multi for a dtype. */
+int fftenkf_max_members_multi(int dtype);
+
 /* Releases cached library state.  The library keeps only its twiddle tables,
  * which are static device arrays filled on first use and live until the
  * process ends, so there is nothing to free: returns FFTENKF_OK. */
@@ -180,7 +208,8 @@ int fftenkf_debug_learned_spectrum(const fftenkf_ens* ens, const void* data, con
 
 /*
  * Profiling hook for the calling thread.  With n == 4, the next
- * fftenkf_analyze or fftenkf_analyze_spectrum records events[0] before sweep 1,
+ * fftenkf_analyze, fftenkf_analyze_spectrum or fftenkf_analyze_multi records
+ * events[0] before sweep 1,
  * events[1] between sweeps 1 and 2, events[2] between sweeps 2 and 3 and
  * events[3] after sweep 3.  With n == 6, the next fftenkf_analyze_learned
  * records them around its five launches (sweep 1, the statistics sweep, the

@@ -63,6 +63,11 @@ EXPORTS = {
     "fftenkf_analyze_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                                 ctypes.c_void_p, ctypes.c_void_p]),
     "fftenkf_release_caches": (ctypes.c_int, []),
+    "fftenkf_analyze_multi": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_uint64, ctypes.c_void_p]),
+    "fftenkf_workspace_bytes_multi": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                        ctypes.c_int]),
+    "fftenkf_max_members_multi": (ctypes.c_int, [ctypes.c_int]),
     "fftenkf_debug_fft2": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "fftenkf_debug_learned_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.POINTER(Mlp),
                                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -147,6 +152,28 @@ def analyze(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, f
     st = lib().fftenkf_analyze(ctypes.byref(e), data.data_ptr(), _ptr(R_t), ctypes.c_uint64(seed & (2**64 - 1)),
                                out.data_ptr())
     _check(st, "fftenkf_analyze")
+    return out
+
+
+def analyze_multi(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, float], seed: int,
+                  out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Multi-block analysis (eq. (6)): ens [N, M, ny, nx] member-major, data observing block 0."""
+    if ens.dim() != 4 or not ens.is_cuda or not ens.is_contiguous():
+        raise ValueError("ens must be a contiguous device tensor [N, M, ny, nx]")
+    N, M, ny, nx = ens.shape
+    R_t, r = _rspec(R_spec)
+    code = _dtype_code(ens)
+    if workspace is None:
+        need = int(lib().fftenkf_workspace_bytes_multi(N, M, ny, nx, code))
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=ens.device)
+    e = Ens(n_members=N, ny=ny, nx=nx, dtype=code, members=ens.data_ptr(), workspace=workspace.data_ptr(),
+            workspace_bytes=workspace.numel(), stream=torch.cuda.current_stream(ens.device).cuda_stream,
+            r_scalar=float(r))
+    if out is None:
+        out = torch.empty_like(ens)
+    st = lib().fftenkf_analyze_multi(ctypes.byref(e), M, data.data_ptr(), _ptr(R_t),
+                                     ctypes.c_uint64(seed & (2**64 - 1)), out.data_ptr())
+    _check(st, "fftenkf_analyze_multi")
     return out
 
 

@@ -47,6 +47,13 @@ hipError_t launch_k2_f32(const K2Args& a, hipStream_t s) {
   }
 }
 
+hipError_t launch_k6_f32(const K6Args&, hipStream_t);
+hipError_t launch_k6_f64(const K6Args&, hipStream_t);
+
+hipError_t launch_k6(const K6Args& a, int dtype, hipStream_t s) {
+  return dtype == FFTENKF_F32 ? launch_k6_f32(a, s) : launch_k6_f64(a, s);
+}
+
 hipError_t launch_k2_f64(const K2Args& a, hipStream_t s) {
   switch (k2_member_bucket(FFTENKF_F64, a.N)) {
     case 4: return launch_k2_f64_n4(a, s);
@@ -382,6 +389,79 @@ int run_fft2(const fftenkf_ens* e, const Plan& plan, int inverse, const void* sp
   return FFTENKF_OK;
 }
 
+// Shape and workspace checks of the multi-block analysis; the plan covers the
+// N * M member fields and d.
+int validate_multi(const fftenkf_ens* e, int M, Plan* plan) {
+  if (e == nullptr) return fail(FFTENKF_EINVAL, "ens is NULL");
+  if (e->dtype != FFTENKF_F32 && e->dtype != FFTENKF_F64) return fail(FFTENKF_EINVAL, "dtype %d is not 0 (f32) or 1 (f64)", e->dtype);
+  if (e->n_members < 2) return fail(FFTENKF_EINVAL, "n_members = %d, eq. (2) needs N >= 2", e->n_members);
+  if (M < 1 || M > kMaxStateBlocks) return fail(FFTENKF_EINVAL, "n_blocks = %d outside [1, %d]", M, kMaxStateBlocks);
+  if (!pow2_in_range(e->ny) || !pow2_in_range(e->nx))
+    return fail(FFTENKF_EUNSUPPORTED, "grid %d x %d: each side must be a power of two in [8, 4096]", e->ny, e->nx);
+  if (e->n_members > fftenkf_max_members_multi(e->dtype))
+    return fail(FFTENKF_EUNSUPPORTED, "n_members = %d exceeds %d for the multi-block analysis", e->n_members,
+                fftenkf_max_members_multi(e->dtype));
+  *plan = make_plan(e->n_members * M, e->ny, e->nx, e->dtype);
+  if (e->members == nullptr) return fail(FFTENKF_EINVAL, "members is NULL");
+  if (e->workspace == nullptr) return fail(FFTENKF_EINVAL, "workspace is NULL");
+  if (e->workspace_bytes < plan->ws_bytes)
+    return fail(FFTENKF_EINVAL, "workspace of %zu bytes, %zu needed", e->workspace_bytes, plan->ws_bytes);
+  if (misaligned(e->members, 16)) return fail(FFTENKF_EINVAL, "members is not 16-byte aligned");
+  if (misaligned(e->workspace, 256)) return fail(FFTENKF_EINVAL, "workspace is not 256-byte aligned");
+  return FFTENKF_OK;
+}
+
+// Sweep 1 over the N * M member fields and d, the multi-block spectral sweep, sweep 3.
+int run_multi(const fftenkf_ens* e, int M, const Plan& plan, const void* data, const void* R_spec, uint64_t seed,
+              void* out) {
+  if (t_fail_next != 0) {
+    const int st = t_fail_next;
+    t_fail_next = 0;
+    return fail(st, "failure forced by fftenkf_debug_fail_next");
+  }
+  hipStream_t stream = static_cast<hipStream_t>(e->stream);
+  const void* tab = nullptr;
+  hipError_t err = twiddle_table(e->dtype, &tab);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
+  char* ws = static_cast<char*>(e->workspace);
+  void* ws_main = ws;
+  void* ws_nyq = ws + plan.off_nyq;
+  const int fields = e->n_members * M;
+  if (!(t_events_on && t_nevents == 4)) t_events_on = false;
+  err = mark(0, stream);
+  K1Args a1{e->members, data, fields, e->ny, e->nx, plan.R, plan.L, ws_main, ws_nyq, tab};
+  if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
+  if (err == hipSuccess) err = mark(1, stream);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 1 launch: %s", hipGetErrorString(err));
+  K6Args a6{};
+  a6.ws_main = ws_main;
+  a6.ws_nyq = ws_nyq;
+  a6.R_spec = R_spec;
+  a6.r_scalar = e->r_scalar;
+  a6.N = e->n_members;
+  a6.M = M;
+  a6.ny = e->ny;
+  a6.nx = e->nx;
+  a6.R = plan.R;
+  a6.L = plan.L;
+  a6.C = plan.C;
+  a6.units_main = plan.units_main;
+  a6.units_total = plan.units_total;
+  a6.group_xcd = plan.group_xcd;
+  a6.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  a6.key1 = (uint32_t)(seed >> 32);
+  a6.tab = tab;
+  err = launch_k6(a6, e->dtype, stream);
+  if (err == hipSuccess) err = mark(2, stream);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "multi-block sweep launch: %s", hipGetErrorString(err));
+  K3Args a3{ws_main, ws_nyq, fields, e->ny, e->nx, plan.R, plan.L, out, tab};
+  err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
+  if (err == hipSuccess) err = mark(3, stream);
+  t_events_on = false;
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 3 launch: %s", hipGetErrorString(err));
+  return FFTENKF_OK;
+}
+
 // The eight weight arrays of the perceptron: present and aligned (host-side
 // checks), then device memory of the current device.
 int check_mlp(const fftenkf_mlp* m, bool device) {
@@ -619,6 +699,58 @@ int fftenkf_debug_fft2(const fftenkf_ens* e, int inverse, const void* spectra, v
     st = check_pointers(ptrs, 4);
     if (st != FFTENKF_OK) return st;
     return run_fft2(e, plan, inverse, spectra, out);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+int fftenkf_max_members_multi(int dtype) {
+  if (dtype == FFTENKF_F32) return kMaxMembersMultiF32;
+  if (dtype == FFTENKF_F64) return kMaxMembersMultiF64;
+  return 0;
+}
+
+size_t fftenkf_workspace_bytes_multi(int n_members, int n_blocks, int ny, int nx, int dtype) {
+  if ((dtype != FFTENKF_F32 && dtype != FFTENKF_F64) || n_members < 2 || n_blocks < 1 || n_blocks > kMaxStateBlocks ||
+      !pow2_in_range(ny) || !pow2_in_range(nx))
+    return 0;
+  return make_plan(n_members * n_blocks, ny, nx, dtype).ws_bytes;
+}
+
+int fftenkf_analyze_multi(const fftenkf_ens* e, int n_blocks, const void* data, const void* R_spec, uint64_t seed,
+                          void* out) {
+  try {
+    Plan plan;
+    int st = validate_multi(e, n_blocks, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (data == nullptr) return fail(FFTENKF_EINVAL, "data is NULL");
+    if (out == nullptr) return fail(FFTENKF_EINVAL, "out is NULL");
+    if (misaligned(data, 16) || misaligned(out, 16) || (R_spec != nullptr && misaligned(R_spec, 16)))
+      return fail(FFTENKF_EINVAL, "data, R_spec and out must be 16-byte aligned");
+    if (R_spec == nullptr && !(e->r_scalar >= 0.0))
+      return fail(FFTENKF_EINVAL, "r_scalar must be >= 0 when R_spec is NULL");
+    const size_t s = dsize(e->dtype);
+    const size_t field = (size_t)e->ny * e->nx * s;
+    const size_t ens_b = field * e->n_members * n_blocks;
+    const size_t rs_b = (size_t)e->ny * (e->nx / 2 + 1) * s;
+    const Ptr ptrs[] = {{e->members, ens_b, "members"},
+                        {data, field, "data"},
+                        {R_spec, rs_b, "R_spec"},
+                        {out, ens_b, "out"},
+                        {e->workspace, plan.ws_bytes, "workspace"}};
+    for (int i = 0; i < 5; ++i)
+      for (int j = i + 1; j < 5; ++j) {
+        if (ptrs[i].p == nullptr || ptrs[j].p == nullptr) continue;
+        const bool in_place = (i == 0 && j == 3 && ptrs[i].p == ptrs[j].p);
+        if (!in_place && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+      }
+    st = check_pointers(ptrs, 5);
+    if (st == FFTENKF_OK)
+      st = check_spectrum_values(R_spec, (size_t)e->ny * (e->nx / 2 + 1), e->dtype,
+                                 static_cast<hipStream_t>(e->stream), "R_spec");
+    if (st != FFTENKF_OK) return st;
+    return run_multi(e, n_blocks, plan, data, R_spec, seed, out);
   } catch (...) {
     return fail(FFTENKF_EDEVICE, "internal error");
   }

@@ -13,13 +13,7 @@
 // exchanges between passes go through two LDS buffers in turn (one block
 // synchronisation each); every field's loads are issued before any transform.
 //
-// Main units cover kx < nx/2 ([NF][R][L][nx/2]: C adjacent kx); the Nyquist
-// column kx = nx/2 ([NF][L][R]) is covered by extra units over C adjacent k2,
-// placed first in the grid so they do not trail.  A unit's row segments are C
-// complex values; when that is less than a 128-byte line, the G units sharing
-// each line are given to blocks b, b + 8, .., b + 8 (G - 1), which the hardware
-// sends to the same XCD one after the other, so the later reads of every line
-// are L2 hits rather than further HBM fetches.
+// The unit geometry (main and Nyquist units, XCD grouping) is spectral_unit.hpp.
 #pragma once
 
 #include <float.h>
@@ -27,6 +21,7 @@
 #include "fft_core.hpp"
 #include "kernels.hpp"
 #include "philox.hpp"
+#include "spectral_unit.hpp"
 
 namespace fftenkf {
 
@@ -70,41 +65,13 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   const int nxh = a.nx >> 1, nh = nxh + 1;
 
   // unit geometry: a uniform base pointer, a uniform field stride and per-thread
-  // 32-bit byte offsets of the P elements (invalid Nyquist columns read column 0
-  // and never write)
-  int k2, kx;
-  bool valid;
-  V2<T>* ubase;
-  uint32_t fstride;  // elements between fields
-  uint32_t sy;       // elements between consecutive y1
-  int cc;
-  const int units_nyq = a.units_total - a.units_main;
-  if (unit >= units_nyq) {
-    int um = unit - units_nyq;
-    if (a.group_xcd > 1) {
-      const int G = a.group_xcd;  // a power of two
-      const int x = um & 7, q = um >> 3;
-      um = G * (((q / G) << 3) + x) + (q & (G - 1));
-    }
-    const int nchunk = nxh / C;
-    k2 = um / nchunk;
-    const int kxc = um - k2 * nchunk;
-    kx = kxc * C + c;
-    valid = true;
-    ubase = static_cast<V2<T>*>(a.ws_main) + (size_t)k2 * L * nxh + (size_t)kxc * C;
-    fstride = (uint32_t)ny * (uint32_t)nxh;
-    sy = (uint32_t)nxh;
-    cc = c;
-  } else {
-    const int v = unit;
-    k2 = v * C + c;
-    kx = nxh;
-    valid = k2 < R;
-    ubase = static_cast<V2<T>*>(a.ws_nyq) + (size_t)v * C;
-    fstride = (uint32_t)ny;
-    sy = (uint32_t)R;
-    cc = valid ? c : 0;
-  }
+  // 32-bit byte offsets of the P elements
+  const SpectralUnit<T> g = spectral_unit<T>(a.ws_main, a.ws_nyq, unit, c, C, R, L, ny, nxh, a.units_main,
+                                             a.units_total, a.group_xcd);
+  const int k2 = g.k2, kx = g.kx, cc = g.cc;
+  const bool valid = g.valid;
+  V2<T>* const ubase = g.ubase;
+  const uint32_t fstride = g.fstride, sy = g.sy;
   uint32_t voff[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) voff[i] = ((uint32_t)(t2 + TF2 * i) * sy + (uint32_t)cc) * (uint32_t)sizeof(V2<T>);

@@ -1,0 +1,20 @@
+#include "k6_multiblock.hpp"
+namespace fftenkf {
+hipError_t launch_k6_f64(const K6Args& a, hipStream_t s) {
+  if (a.N > 4) return hipErrorInvalidValue;
+  switch (a.L) {
+    case 1: return launch_k6_shape<double, 1, 4>(a, s);
+    case 2: return launch_k6_shape<double, 2, 4>(a, s);
+    case 4: return launch_k6_shape<double, 4, 4>(a, s);
+    case 8: return launch_k6_shape<double, 8, 4>(a, s);
+    case 16: return launch_k6_shape<double, 16, 4>(a, s);
+    case 32: return launch_k6_shape<double, 32, 4>(a, s);
+    case 64: return launch_k6_shape<double, 64, 4>(a, s);
+    case 128: return launch_k6_shape<double, 128, 4>(a, s);
+    case 256: return launch_k6_shape<double, 256, 4>(a, s);
+    case 512: return launch_k6_shape<double, 512, 4>(a, s);
+    case 1024: return launch_k6_shape<double, 1024, 4>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace fftenkf

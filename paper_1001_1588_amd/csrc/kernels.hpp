@@ -66,6 +66,18 @@ struct K2Args {
   const void* tab;
 };
 
+// Multi-block spectral sweep: member k of block j is field k * M + j, d is
+// field N * M; the other fields as in K2Args.
+struct K6Args {
+  void* ws_main;
+  void* ws_nyq;
+  const void* R_spec;  // [ny][nx/2+1] or nullptr
+  double r_scalar;
+  int N, M, ny, nx, R, L, C, units_main, units_total, group_xcd;
+  uint32_t key0, key1;
+  const void* tab;
+};
+
 struct K3Args {
   const void* ws_main;
   const void* ws_nyq;
@@ -81,11 +93,16 @@ constexpr int k2_threads_target = 256;
 // Largest member count held in registers by the fused spectral sweep.
 constexpr int kMaxMembersF32 = 24;
 constexpr int kMaxMembersF64 = 8;
+// The multi-block sweep holds two register sets of members.
+constexpr int kMaxMembersMultiF32 = 12;
+constexpr int kMaxMembersMultiF64 = 4;
+constexpr int kMaxStateBlocks = 64;  // blocks of the multi-block analysis
 
 hipError_t launch_k1_f32(const K1Args& a, hipStream_t s);
 hipError_t launch_k1_f64(const K1Args& a, hipStream_t s);
 hipError_t launch_k2_f32(const K2Args& a, hipStream_t s);
 hipError_t launch_k2_f64(const K2Args& a, hipStream_t s);
+hipError_t launch_k6(const K6Args& a, int dtype, hipStream_t s);
 hipError_t launch_k3_f32(const K3Args& a, hipStream_t s);
 hipError_t launch_k3_f64(const K3Args& a, hipStream_t s);
 

@@ -1,0 +1,64 @@
+// Geometry of one unit of the spectral sweep, shared by the single-block and
+// multi-block forms.
+//
+// Main units cover kx < nx/2 ([NF][R][L][nx/2]: C adjacent kx of one k2); the
+// Nyquist column kx = nx/2 ([NF][L][R]) is covered by extra units over C
+// adjacent k2, placed first in the grid so they do not trail.  A unit's row
+// segments are C complex values; when that is less than a 128-byte line, the G
+// units sharing each line are given to blocks b, b + 8, .., b + 8 (G - 1),
+// which the hardware sends to the same XCD one after the other, so the later
+// reads of every line are L2 hits rather than further HBM fetches.
+#pragma once
+
+#include "fft_core.hpp"
+
+namespace fftenkf {
+
+template <typename T>
+struct SpectralUnit {
+  int k2, kx;         // this thread's column: frequency k2 of the radix-R stage and kx
+  bool valid;         // false for padding threads of the last Nyquist unit
+  V2<T>* ubase;       // uniform base of field 0 of this unit
+  uint32_t fstride;   // elements between fields
+  uint32_t sy;        // elements between consecutive y1 (or k1)
+  int cc;             // this thread's column offset from ubase (0 if not valid)
+};
+
+// Thread column c < C of block `unit`; invalid Nyquist columns read column 0
+// and never write.
+template <typename T>
+__device__ __forceinline__ SpectralUnit<T> spectral_unit(void* ws_main, void* ws_nyq, int unit, int c, int C, int R,
+                                                         int L, int ny, int nxh, int units_main, int units_total,
+                                                         int group_xcd) {
+  SpectralUnit<T> g;
+  const int units_nyq = units_total - units_main;
+  if (unit >= units_nyq) {
+    int um = unit - units_nyq;
+    if (group_xcd > 1) {
+      const int G = group_xcd;  // a power of two
+      const int x = um & 7, q = um >> 3;
+      um = G * (((q / G) << 3) + x) + (q & (G - 1));
+    }
+    const int nchunk = nxh / C;
+    g.k2 = um / nchunk;
+    const int kxc = um - g.k2 * nchunk;
+    g.kx = kxc * C + c;
+    g.valid = true;
+    g.ubase = static_cast<V2<T>*>(ws_main) + (size_t)g.k2 * L * nxh + (size_t)kxc * C;
+    g.fstride = (uint32_t)ny * (uint32_t)nxh;
+    g.sy = (uint32_t)nxh;
+    g.cc = c;
+  } else {
+    const int v = unit;
+    g.k2 = v * C + c;
+    g.kx = nxh;
+    g.valid = g.k2 < R;
+    g.ubase = static_cast<V2<T>*>(ws_nyq) + (size_t)v * C;
+    g.fstride = (uint32_t)ny;
+    g.sy = (uint32_t)R;
+    g.cc = g.valid ? c : 0;
+  }
+  return g;
+}
+
+}  // namespace fftenkf

@@ -161,3 +161,21 @@ def test_release_caches_and_fft2_arguments(built_lib):
     assert lib.fftenkf_debug_fft2(ctypes.byref(e), 1, None, 0x300000) == _lib.EINVAL       # inverse needs spectra
     assert lib.fftenkf_debug_fft2(ctypes.byref(e), 0, None, 0x300008) == _lib.EINVAL       # misaligned
     assert lib.fftenkf_debug_fft2(ctypes.byref(e), 0, None, 0x100000 + 64) == _lib.EINVAL  # out overlaps members
+
+
+def test_multi_validation_and_workspace(built_lib):
+    lib = _lib.lib()
+    e = _ens()
+    call_m = lambda ens, M, **kw: lib.fftenkf_analyze_multi(ctypes.byref(ens), M, kw.get("data", 0x200000),  # noqa: E731
+                                                            None, 1, kw.get("out", 0x300000))
+    assert call_m(e, 0) == _lib.EINVAL
+    assert call_m(e, 65) == _lib.EINVAL
+    assert call_m(_ens(n_members=13), 2) == _lib.EUNSUPPORTED
+    assert call_m(_ens(n_members=5, dtype=_lib.F64), 2) == _lib.EUNSUPPORTED
+    assert call_m(_ens(ny=12), 2) == _lib.EUNSUPPORTED
+    assert call_m(e, 2, out=0x100000 + 16 * 16 * 4 * 4) == _lib.EINVAL   # out overlaps members (N*M fields)
+    assert lib.fftenkf_max_members_multi(0) == 12 and lib.fftenkf_max_members_multi(1) == 4
+    # the multi-block workspace is that of an analysis with N * M members
+    for (N, M, ny, nx, dt) in [(10, 4, 1024, 1024, 0), (3, 2, 16, 8, 1)]:
+        assert lib.fftenkf_workspace_bytes_multi(N, M, ny, nx, dt) == lib.fftenkf_workspace_bytes(N * M, ny, nx, dt)
+    assert lib.fftenkf_workspace_bytes_multi(4, 0, 16, 16, 0) == 0

@@ -1,0 +1,81 @@
+"""Multi-block analysis (Section 2.2) on the GPU, through the C ABI, against the
+float64 oracle (oracle/multiblock.py).
+
+Bar: relative L2 over all members, blocks and points <= 1e-5 in float32 and
+<= 1e-10 in float64, as for the single-block analysis: every block's update is
+the same float32 arithmetic (transforms, sums over members, one division per
+bin) applied through the cross-covariance gain."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import multiblock
+from paper_1001_1588_amd import _lib, twin
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {np.float32: 1e-5, np.float64: 1e-10}
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+# (ny, nx, N, M, dtype, R as)
+CASES = [(8, 8, 2, 1, np.float32, "scalar"), (8, 16, 3, 2, np.float64, "array"), (16, 16, 4, 3, np.float32, "array"),
+         (32, 64, 5, 2, np.float32, "scalar"), (64, 32, 6, 4, np.float32, "array"), (64, 64, 4, 2, np.float64, "scalar"),
+         (128, 128, 8, 3, np.float32, "array"), (256, 128, 10, 4, np.float32, "scalar"),
+         (128, 256, 12, 2, np.float32, "array"), (64, 1024, 7, 5, np.float32, "array")]
+
+
+def case_id(c):
+    return f"{c[0]}x{c[1]}-N{c[2]}-M{c[3]}-{np.dtype(c[4]).name}-{c[5]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=case_id)
+def test_multiblock_matches_oracle(case):
+    ny, nx, N, M, dt, R_as = case
+    Ls = tuple(float(x) for x in (2, 4, 8, 16, 32)[:M])
+    tw = twin.make_multiblock_twin(ny, nx, N, seed=ny + 3 * nx + 7 * N + M, Ls=Ls, dtype=dt)
+    R = dev(tw.R_spec) if R_as == "array" else float(tw.r)
+    out = _lib.analyze_multi(dev(tw.ens), dev(tw.data), R, tw.seed)
+    torch.cuda.synchronize()
+    ref = multiblock.analyze_multi(tw.ens, tw.data, tw.R_spec, tw.seed,
+                                   method="matmul" if ny * nx <= 65536 else "fft")
+    assert rel_l2(out.cpu().numpy(), ref) <= TOL[dt]
+
+
+def test_config_multiblock_1024_n10_m4():
+    """The multi-block configuration at its own size: 4 fields of 1024 x 1024, N = 10, R = 0.02 I."""
+    tw = twin.make_multiblock_twin(1024, 1024, 10, seed=77, dtype=np.float32)
+    out = _lib.analyze_multi(dev(tw.ens), dev(tw.data), dev(tw.R_spec), tw.seed)
+    torch.cuda.synchronize()
+    ref = multiblock.analyze_multi(tw.ens, tw.data, tw.R_spec, tw.seed, method="fft")
+    got = out.cpu().numpy()
+    assert rel_l2(got, ref) <= 1e-5
+    for j in range(4):   # every block, not only the bulk of the norm
+        assert rel_l2(got[:, j], ref[:, j]) <= 1e-5
+
+
+def test_one_block_equals_single_block_analysis():
+    tw = twin.random_ensemble(128, 64, 6, seed=5, dtype=np.float32, R_kind="spectral")
+    R = dev(tw.R_spec)
+    single = _lib.analyze(dev(tw.ens), dev(tw.data), R, tw.seed)
+    multi = _lib.analyze_multi(dev(tw.ens[:, None]), dev(tw.data), R, tw.seed)
+    torch.cuda.synchronize()
+    s, m = single.cpu().numpy().astype(np.float64), multi[:, 0].cpu().numpy().astype(np.float64)
+    assert rel_l2(m, s) <= 2e-7
+
+
+def test_in_place_and_deterministic():
+    tw = twin.make_multiblock_twin(64, 64, 5, seed=9, Ls=(2.0, 4.0, 8.0), dtype=np.float32)
+    a = _lib.analyze_multi(dev(tw.ens), dev(tw.data), 0.02, tw.seed)
+    ens = dev(tw.ens)
+    b = _lib.analyze_multi(ens, dev(tw.data), 0.02, tw.seed, out=ens)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
