@@ -160,6 +160,49 @@ size_t fftenkf_workspace_bytes_multi(int n_members, int n_blocks, int ny, int nx
 /* Largest N of fftenkf_analyze_multi for a dtype. */
 int fftenkf_max_members_multi(int dtype);
 
+/*
+ * A batch of independent analyses (eq. (3) with eq. (2), exactly as
+ * fftenkf_analyze, one per filter) with one member count and dtype but grids
+ * of any supported sizes.  Filters on the same grid share launches: each of the
+ * three sweeps runs once per grid size for up to 40 filters at a time, the
+ * filter selected by the second grid dimension, and the per-filter arguments
+ * travel by value in the launch, so the whole batch can be captured in a HIP
+ * graph (stream capture) and replayed; FFTENKF_CHECK must then be unset, since
+ * its check synchronises the stream.  Each filter's output is bitwise equal to
+ * fftenkf_analyze on the same arguments.
+ */
+typedef struct fftenkf_filter {
+  int32_t ny, nx;         /* grid of this filter, powers of two in [8, 4096] */
+  const void* members;    /* device [N][ny][nx] */
+  const void* data;       /* device [ny][nx] */
+  const void* R_spec;     /* device [ny][nx/2+1], or NULL for r_scalar */
+  void* out;              /* device [N][ny][nx]; may equal members */
+  void* workspace;        /* device, fftenkf_workspace_bytes(N, ny, nx, dtype) bytes, 256-byte aligned */
+  size_t workspace_bytes;
+  double r_scalar;        /* R = r_scalar * I when R_spec is NULL */
+  uint64_t seed;          /* perturbations of this filter (the convention of fftenkf_analyze) */
+} fftenkf_filter;
+
+/* Enqueues every filter's analysis on `stream` (hipStream_t, NULL = default).
+ * Arguments are validated first (as for fftenkf_analyze, per filter; what a
+ * filter writes may overlap no other buffer of the batch); on error nothing is
+ * enqueued. */
+int fftenkf_analyze_batch(int n_members, int dtype, const fftenkf_filter* filters, int n_filters, void* stream);
+
+/*
+ * Tile schedule.  The y transform is split as ny = R * L between sweeps 1/3 (R
+ * rows per tile, a radix-R stage in registers) and sweep 2 (length-L
+ * transforms).  fftenkf_tile_rows_options lists the R compiled for a grid and
+ * dtype (up to `capacity` of them into `rows`; returns how many there are);
+ * fftenkf_set_tile_rows chooses one for every later call on that grid and
+ * dtype in this process (0 restores the default; FFTENKF_EUNSUPPORTED if not
+ * compiled); fftenkf_tile_rows returns the R in use.  The workspace size
+ * depends on R: query it after choosing.
+ */
+int fftenkf_tile_rows_options(int ny, int nx, int dtype, int* rows, int capacity);
+int fftenkf_set_tile_rows(int ny, int nx, int dtype, int rows);
+int fftenkf_tile_rows(int ny, int nx, int dtype);
+
 /* Releases cached library state.  The library keeps only its twiddle tables,
  * which are static device arrays filled on first use and live until the
  * process ends, so there is nothing to free: returns FFTENKF_OK. */

@@ -44,6 +44,23 @@ class Mlp(ctypes.Structure):
 MLP_SHAPES = {"W1": (26, 64), "b1": (64,), "W2": (64, 64), "b2": (64,), "W3": (64, 64), "b3": (64,),
               "w4": (64,), "b4": (1,)}
 
+class Filter(ctypes.Structure):
+    """Mirror of struct fftenkf_filter."""
+
+    _fields_ = [
+        ("ny", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("members", ctypes.c_void_p),
+        ("data", ctypes.c_void_p),
+        ("R_spec", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("r_scalar", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 EXPORTS = {
@@ -63,6 +80,12 @@ EXPORTS = {
     "fftenkf_analyze_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                                 ctypes.c_void_p, ctypes.c_void_p]),
     "fftenkf_release_caches": (ctypes.c_int, []),
+    "fftenkf_analyze_batch": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Filter), ctypes.c_int,
+                                             ctypes.c_void_p]),
+    "fftenkf_tile_rows_options": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "fftenkf_set_tile_rows": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "fftenkf_tile_rows": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "fftenkf_analyze_multi": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_uint64, ctypes.c_void_p]),
     "fftenkf_workspace_bytes_multi": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -286,6 +309,79 @@ def debug_irfft2(spectra: torch.Tensor, nx: int) -> torch.Tensor:
     e, ws = _make_ens(out, None, 0.0)
     _check(lib().fftenkf_debug_fft2(ctypes.byref(e), 1, spectra.data_ptr(), out.data_ptr()), "fftenkf_debug_fft2")
     return out
+
+
+def tile_rows_options(ny: int, nx: int, dtype: torch.dtype) -> list:
+    code = F32 if dtype == torch.float32 else F64
+    buf = (ctypes.c_int * 8)()
+    n = lib().fftenkf_tile_rows_options(ny, nx, code, buf, 8)
+    return [int(buf[i]) for i in range(min(n, 8))]
+
+
+def set_tile_rows(ny: int, nx: int, dtype: torch.dtype, rows: int) -> None:
+    code = F32 if dtype == torch.float32 else F64
+    _check(lib().fftenkf_set_tile_rows(ny, nx, code, rows), "fftenkf_set_tile_rows")
+
+
+def tile_rows(ny: int, nx: int, dtype: torch.dtype) -> int:
+    return int(lib().fftenkf_tile_rows(ny, nx, F32 if dtype == torch.float32 else F64))
+
+
+class Batch:
+    """Independent analyses of uneven grids (fftenkf_analyze_batch), with the
+    device buffers for them: inputs [N, ny, nx] per filter, one workspace slab
+    cut into per-filter pieces, outputs.  `run()` enqueues the whole batch on
+    the current stream; `capture()` records it into a graph that `replay()`
+    runs again on the same buffers."""
+
+    def __init__(self, ens: list, data: list, R: list, seeds: list, out: Optional[list] = None):
+        if not (len(ens) == len(data) == len(R) == len(seeds)):
+            raise ValueError("ens, data, R and seeds need one entry per filter")
+        self.ens, self.data, self.R, self.seeds = ens, data, R, seeds
+        self.N = int(ens[0].shape[0])
+        self.dtype = ens[0].dtype
+        code = _dtype_code(ens[0])
+        self.out = out if out is not None else [torch.empty_like(e) for e in ens]
+        sizes = [(workspace_bytes(self.N, e.shape[1], e.shape[2], self.dtype) + 255) // 256 * 256 for e in ens]
+        self.workspace = torch.empty(max(sum(sizes), 256), dtype=torch.uint8, device=ens[0].device)
+        base, off = self.workspace.data_ptr(), 0
+        arr = (Filter * len(ens))()
+        for i, e in enumerate(ens):
+            if e.dim() != 3 or not e.is_cuda or not e.is_contiguous() or e.dtype != self.dtype or e.shape[0] != self.N:
+                raise ValueError(f"filter {i}: ens must be a contiguous [N, ny, nx] device tensor like the others")
+            R_t, r = _rspec(R[i])
+            arr[i] = Filter(ny=e.shape[1], nx=e.shape[2], members=e.data_ptr(), data=data[i].data_ptr(),
+                            R_spec=_ptr(R_t), out=self.out[i].data_ptr(), workspace=base + off,
+                            workspace_bytes=sizes[i], r_scalar=float(r), seed=seeds[i] & (2**64 - 1))
+            off += sizes[i]
+        self._filters = arr
+        self._code = code
+        self.graph = None
+
+    def run(self) -> list:
+        st = lib().fftenkf_analyze_batch(self.N, self._code, self._filters, len(self._filters),
+                                         torch.cuda.current_stream(self.ens[0].device).cuda_stream)
+        _check(st, "fftenkf_analyze_batch")
+        return self.out
+
+    def capture(self) -> None:
+        """Record the batch into a HIP graph (after one eager run, which sets up
+        the library's tables and kernel attributes outside the capture)."""
+        self.run()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(self.graph, stream=s):
+                self.run()
+        torch.cuda.current_stream().wait_stream(s)
+
+    def replay(self) -> list:
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+        return self.out
 
 
 def debug_fail_next(status: int) -> None:

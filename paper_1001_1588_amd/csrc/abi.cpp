@@ -9,7 +9,10 @@
 #include <string.h>
 
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.hpp"
@@ -46,6 +49,19 @@ hipError_t launch_k2_f32(const K2Args& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
 }
+
+hipError_t launch_k1_batch_f32(const BatchArgs&, int, hipStream_t);
+hipError_t launch_k1_batch_f64(const BatchArgs&, int, hipStream_t);
+hipError_t launch_k3_batch_f32(const BatchArgs&, int, hipStream_t);
+hipError_t launch_k3_batch_f64(const BatchArgs&, int, hipStream_t);
+hipError_t launch_k2_batch_f32_n4(const BatchArgs&, hipStream_t);
+hipError_t launch_k2_batch_f32_n8(const BatchArgs&, hipStream_t);
+hipError_t launch_k2_batch_f32_n12(const BatchArgs&, hipStream_t);
+hipError_t launch_k2_batch_f32_n16(const BatchArgs&, hipStream_t);
+hipError_t launch_k2_batch_f32_n20(const BatchArgs&, hipStream_t);
+hipError_t launch_k2_batch_f32_n24(const BatchArgs&, hipStream_t);
+hipError_t launch_k2_batch_f64_n4(const BatchArgs&, hipStream_t);
+hipError_t launch_k2_batch_f64_n8(const BatchArgs&, hipStream_t);
 
 hipError_t launch_k6_f32(const K6Args&, hipStream_t);
 hipError_t launch_k6_f64(const K6Args&, hipStream_t);
@@ -104,10 +120,39 @@ int rows_per_tile(int dtype, int nx) {
   return nx <= 2048 ? 8 : 4;
 }
 
+// Row counts R of the sweep-1/3 tiles compiled for a dtype and nx (each also
+// needs R <= ny).
+int tile_rows_options(int dtype, int nx, int* out) {
+  if (dtype == FFTENKF_F32) {
+    if (nx <= 2048) {
+      out[0] = 8;
+      out[1] = 16;
+      return 2;
+    }
+    out[0] = 8;
+    return 1;
+  }
+  out[0] = nx <= 2048 ? 8 : 4;
+  return 1;
+}
+
+// Tile rows chosen by a tuner for a grid, process-wide; the default otherwise.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune;
+
+int tile_rows(int ny, int nx, int dtype) {
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(ny, nx, dtype));
+    if (it != g_tune.end()) return it->second;
+  }
+  const int rmax = rows_per_tile(dtype, nx);
+  return ny < rmax ? ny : rmax;
+}
+
 Plan make_plan(int N, int ny, int nx, int dtype) {
   Plan p{};
-  const int rmax = rows_per_tile(dtype, nx);
-  p.R = ny < rmax ? ny : rmax;
+  p.R = tile_rows(ny, nx, dtype);
   p.L = ny / p.R;
   p.P = k2_points(p.L);
   const int tf2 = p.L / p.P;
@@ -462,6 +507,110 @@ int run_multi(const fftenkf_ens* e, int M, const Plan& plan, const void* data, c
   return FFTENKF_OK;
 }
 
+hipError_t launch_k2_batch(const BatchArgs& b, int dtype, hipStream_t s) {
+  switch (k2_member_bucket(dtype, b.N) * (dtype == FFTENKF_F32 ? 1 : -1)) {
+    case 4: return launch_k2_batch_f32_n4(b, s);
+    case 8: return launch_k2_batch_f32_n8(b, s);
+    case 12: return launch_k2_batch_f32_n12(b, s);
+    case 16: return launch_k2_batch_f32_n16(b, s);
+    case 20: return launch_k2_batch_f32_n20(b, s);
+    case 24: return launch_k2_batch_f32_n24(b, s);
+    case -4: return launch_k2_batch_f64_n4(b, s);
+    case -8: return launch_k2_batch_f64_n8(b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// One filter of a batch: the checks of fftenkf_analyze, host-side ones only.
+int validate_filter(const fftenkf_filter& f, int N, int dtype, int i, Plan* plan) {
+  if (!pow2_in_range(f.ny) || !pow2_in_range(f.nx))
+    return fail(FFTENKF_EUNSUPPORTED, "filter %d: grid %d x %d: each side must be a power of two in [8, 4096]", i,
+                f.ny, f.nx);
+  *plan = make_plan(N, f.ny, f.nx, dtype);
+  if (f.members == nullptr || f.data == nullptr || f.out == nullptr || f.workspace == nullptr)
+    return fail(FFTENKF_EINVAL, "filter %d: members, data, out and workspace are required", i);
+  if (f.workspace_bytes < plan->ws_bytes)
+    return fail(FFTENKF_EINVAL, "filter %d: workspace of %zu bytes, %zu needed", i, f.workspace_bytes, plan->ws_bytes);
+  if (misaligned(f.members, 16) || misaligned(f.data, 16) || misaligned(f.out, 16) ||
+      (f.R_spec != nullptr && misaligned(f.R_spec, 16)) || misaligned(f.workspace, 256))
+    return fail(FFTENKF_EINVAL, "filter %d: pointers must be 16-byte (workspace 256-byte) aligned", i);
+  if (f.R_spec == nullptr && !(f.r_scalar >= 0.0))
+    return fail(FFTENKF_EINVAL, "filter %d: r_scalar must be >= 0 when R_spec is NULL", i);
+  return FFTENKF_OK;
+}
+
+// The regions a filter reads (members, data, R_spec) and writes (out, workspace).
+void filter_regions(const fftenkf_filter& f, int N, int dtype, const Plan& plan, Ptr* r) {
+  const size_t s = dsize(dtype);
+  const size_t field = (size_t)f.ny * f.nx * s;
+  r[0] = {f.members, field * N, "members"};
+  r[1] = {f.data, field, "data"};
+  r[2] = {f.R_spec, (size_t)f.ny * (f.nx / 2 + 1) * s, "R_spec"};
+  r[3] = {f.out, field * N, "out"};
+  r[4] = {f.workspace, plan.ws_bytes, "workspace"};
+}
+
+// The three sweeps of every filter: filters on the same grid share launches,
+// kMaxBatch at a time, blockIdx.y selecting the filter.
+int run_batch(int N, int dtype, const fftenkf_filter* fs, int n, const std::vector<Plan>& plans, hipStream_t stream) {
+  if (t_fail_next != 0) {
+    const int st = t_fail_next;
+    t_fail_next = 0;
+    return fail(st, "failure forced by fftenkf_debug_fail_next");
+  }
+  const void* tab = nullptr;
+  hipError_t err = twiddle_table(dtype, &tab);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  for (int i = 0; i < n; ++i) groups[std::make_pair(fs[i].ny, fs[i].nx)].push_back(i);
+  for (const auto& g : groups) {
+    const std::vector<int>& idx = g.second;
+    const Plan& plan = plans[idx[0]];
+    for (size_t c0 = 0; c0 < idx.size(); c0 += kMaxBatch) {
+      BatchArgs b{};
+      b.count = (int)std::min<size_t>(kMaxBatch, idx.size() - c0);
+      b.N = N;
+      b.ny = g.first.first;
+      b.nx = g.first.second;
+      b.L = plan.L;
+      b.tab = tab;
+      K2Args& a2 = b.k2;
+      a2.N = N;
+      a2.ny = b.ny;
+      a2.nx = b.nx;
+      a2.R = plan.R;
+      a2.L = plan.L;
+      a2.C = plan.C;
+      a2.units_main = plan.units_main;
+      a2.units_total = plan.units_total;
+      a2.group_xcd = plan.group_xcd;
+      a2.mode = K2_ANALYZE;
+      a2.tab = tab;
+      for (int k = 0; k < b.count; ++k) {
+        const fftenkf_filter& f = fs[idx[c0 + k]];
+        char* ws = static_cast<char*>(f.workspace);
+        BatchFilter& bf = b.f[k];
+        bf.members = f.members;
+        bf.data = f.data;
+        bf.R_spec = f.R_spec;
+        bf.out = f.out;
+        bf.ws_main = ws;
+        bf.ws_nyq = ws + plan.off_nyq;
+        bf.r_scalar = f.r_scalar;
+        bf.key0 = (uint32_t)(f.seed & 0xFFFFFFFFu);
+        bf.key1 = (uint32_t)(f.seed >> 32);
+      }
+      err = dtype == FFTENKF_F32 ? launch_k1_batch_f32(b, plan.R, stream) : launch_k1_batch_f64(b, plan.R, stream);
+      if (err == hipSuccess) err = launch_k2_batch(b, dtype, stream);
+      if (err == hipSuccess)
+        err = dtype == FFTENKF_F32 ? launch_k3_batch_f32(b, plan.R, stream) : launch_k3_batch_f64(b, plan.R, stream);
+      if (err != hipSuccess)
+        return fail(FFTENKF_EDEVICE, "batch launch (%d x %d): %s", b.ny, b.nx, hipGetErrorString(err));
+    }
+  }
+  return FFTENKF_OK;
+}
+
 // The eight weight arrays of the perceptron: present and aligned (host-side
 // checks), then device memory of the current device.
 int check_mlp(const fftenkf_mlp* m, bool device) {
@@ -751,6 +900,85 @@ int fftenkf_analyze_multi(const fftenkf_ens* e, int n_blocks, const void* data, 
                                  static_cast<hipStream_t>(e->stream), "R_spec");
     if (st != FFTENKF_OK) return st;
     return run_multi(e, n_blocks, plan, data, R_spec, seed, out);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+int fftenkf_tile_rows_options(int ny, int nx, int dtype, int* rows, int capacity) {
+  if ((dtype != FFTENKF_F32 && dtype != FFTENKF_F64) || !pow2_in_range(ny) || !pow2_in_range(nx)) return 0;
+  int all[4];
+  const int n = tile_rows_options(dtype, nx, all);
+  int k = 0;
+  for (int i = 0; i < n; ++i)
+    if (all[i] <= ny) {
+      if (rows != nullptr && k < capacity) rows[k] = all[i];
+      ++k;
+    }
+  return k;
+}
+
+int fftenkf_tile_rows(int ny, int nx, int dtype) {
+  if ((dtype != FFTENKF_F32 && dtype != FFTENKF_F64) || !pow2_in_range(ny) || !pow2_in_range(nx)) return 0;
+  return tile_rows(ny, nx, dtype);
+}
+
+int fftenkf_set_tile_rows(int ny, int nx, int dtype, int rows) {
+  if ((dtype != FFTENKF_F32 && dtype != FFTENKF_F64) || !pow2_in_range(ny) || !pow2_in_range(nx))
+    return fail(FFTENKF_EINVAL, "bad grid or dtype");
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const auto key = std::make_tuple(ny, nx, dtype);
+  if (rows == 0) {
+    g_tune.erase(key);
+    return FFTENKF_OK;
+  }
+  int all[4];
+  const int n = tile_rows_options(dtype, nx, all);
+  for (int i = 0; i < n; ++i)
+    if (all[i] == rows && rows <= ny) {
+      g_tune[key] = rows;
+      return FFTENKF_OK;
+    }
+  return fail(FFTENKF_EUNSUPPORTED, "%d tile rows are not compiled for a %d x %d grid of this dtype", rows, ny, nx);
+}
+
+int fftenkf_analyze_batch(int n_members, int dtype, const fftenkf_filter* filters, int n_filters, void* stream) {
+  try {
+    if (dtype != FFTENKF_F32 && dtype != FFTENKF_F64) return fail(FFTENKF_EINVAL, "dtype %d is not 0 or 1", dtype);
+    if (n_members < 2) return fail(FFTENKF_EINVAL, "n_members = %d, eq. (2) needs N >= 2", n_members);
+    if (k2_member_bucket(dtype, n_members) == 0)
+      return fail(FFTENKF_EUNSUPPORTED, "n_members = %d exceeds %d for this dtype", n_members, fftenkf_max_members(dtype));
+    if (n_filters < 0 || (n_filters > 0 && filters == nullptr)) return fail(FFTENKF_EINVAL, "filters is NULL");
+    if (n_filters == 0) return FFTENKF_OK;
+    std::vector<Plan> plans((size_t)n_filters);
+    std::vector<Ptr> regions((size_t)n_filters * 5);
+    for (int i = 0; i < n_filters; ++i) {
+      const int st = validate_filter(filters[i], n_members, dtype, i, &plans[i]);
+      if (st != FFTENKF_OK) return st;
+      filter_regions(filters[i], n_members, dtype, plans[i], &regions[(size_t)i * 5]);
+    }
+    // what a filter writes (out, workspace) may overlap nothing else, except out
+    // == members of the same filter (in place)
+    for (int i = 0; i < n_filters; ++i)
+      for (int w = 3; w < 5; ++w) {
+        const Ptr& a = regions[(size_t)i * 5 + w];
+        for (int j = 0; j < n_filters; ++j)
+          for (int r = 0; r < 5; ++r) {
+            if (i == j && r == w) continue;
+            const Ptr& b = regions[(size_t)j * 5 + r];
+            if (b.p == nullptr) continue;
+            if (i == j && w == 3 && r == 0 && a.p == b.p) continue;
+            if (overlaps(a.p, a.bytes, b.p, b.bytes))
+              return fail(FFTENKF_EINVAL, "filter %d's %s overlaps filter %d's %s", i, a.name, j, b.name);
+          }
+      }
+    int st = check_pointers(regions.data(), (int)regions.size());
+    if (st != FFTENKF_OK) return st;
+    for (int i = 0; i < n_filters && st == FFTENKF_OK; ++i)
+      st = check_spectrum_values(filters[i].R_spec, (size_t)filters[i].ny * (filters[i].nx / 2 + 1), dtype,
+                                 static_cast<hipStream_t>(stream), "R_spec");
+    if (st != FFTENKF_OK) return st;
+    return run_batch(n_members, dtype, filters, n_filters, plans, static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(FFTENKF_EDEVICE, "internal error");
   }

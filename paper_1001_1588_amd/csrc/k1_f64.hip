@@ -1,26 +1,51 @@
 #include "k1_forward.hpp"
 namespace fftenkf {
 template <int NX>
-static hipError_t k1_f64_R(const K1Args& a, hipStream_t s) {
+static hipError_t k1_f64_R(const K1Args& a, int R, hipStream_t s) {
   if constexpr (NX <= 2048) {
-    if (a.R == 8) return launch_k1_shape<double, NX, 8>(a, s);
+    if (R == 8) return launch_k1_shape<double, NX, 8>(a, s);
   } else {
-    if (a.R == 4) return launch_k1_shape<double, NX, 4>(a, s);
+    if (R == 4) return launch_k1_shape<double, NX, 4>(a, s);
   }
   return hipErrorInvalidValue;
 }
 hipError_t launch_k1_f64(const K1Args& a, hipStream_t s) {
+  const int R = a.R;
   switch (a.nx) {
-    case 8: return k1_f64_R<8>(a, s);
-    case 16: return k1_f64_R<16>(a, s);
-    case 32: return k1_f64_R<32>(a, s);
-    case 64: return k1_f64_R<64>(a, s);
-    case 128: return k1_f64_R<128>(a, s);
-    case 256: return k1_f64_R<256>(a, s);
-    case 512: return k1_f64_R<512>(a, s);
-    case 1024: return k1_f64_R<1024>(a, s);
-    case 2048: return k1_f64_R<2048>(a, s);
-    case 4096: return k1_f64_R<4096>(a, s);
+    case 8: return k1_f64_R<8>(a, R, s);
+    case 16: return k1_f64_R<16>(a, R, s);
+    case 32: return k1_f64_R<32>(a, R, s);
+    case 64: return k1_f64_R<64>(a, R, s);
+    case 128: return k1_f64_R<128>(a, R, s);
+    case 256: return k1_f64_R<256>(a, R, s);
+    case 512: return k1_f64_R<512>(a, R, s);
+    case 1024: return k1_f64_R<1024>(a, R, s);
+    case 2048: return k1_f64_R<2048>(a, R, s);
+    case 4096: return k1_f64_R<4096>(a, R, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+template <int NX>
+static hipError_t k1_f64_R_batch(const BatchArgs& a, int R, hipStream_t s) {
+  if constexpr (NX <= 2048) {
+    if (R == 8) return launch_k1_batch_shape<double, NX, 8>(a, s);
+  } else {
+    if (R == 4) return launch_k1_batch_shape<double, NX, 4>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+hipError_t launch_k1_batch_f64(const BatchArgs& a, int R, hipStream_t s) {
+  switch (a.nx) {
+    case 8: return k1_f64_R_batch<8>(a, R, s);
+    case 16: return k1_f64_R_batch<16>(a, R, s);
+    case 32: return k1_f64_R_batch<32>(a, R, s);
+    case 64: return k1_f64_R_batch<64>(a, R, s);
+    case 128: return k1_f64_R_batch<128>(a, R, s);
+    case 256: return k1_f64_R_batch<256>(a, R, s);
+    case 512: return k1_f64_R_batch<512>(a, R, s);
+    case 1024: return k1_f64_R_batch<1024>(a, R, s);
+    case 2048: return k1_f64_R_batch<2048>(a, R, s);
+    case 4096: return k1_f64_R_batch<4096>(a, R, s);
     default: return hipErrorInvalidValue;
   }
 }

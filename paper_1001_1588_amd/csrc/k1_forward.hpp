@@ -24,10 +24,11 @@ struct K1Geom {
   static constexpr int threads = TF * G;
 };
 
+// The work of one block; `block` is its index within one analysis.
 template <typename T, int NX, int R, int SB>
-__global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
-    const T* __restrict__ members, const T* __restrict__ data, int N, int ny, int L,
-    V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq, const V2<T>* __restrict__ tab) {
+__device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* __restrict__ data, int N, int ny,
+                                        int L, V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq,
+                                        const V2<T>* __restrict__ tab, unsigned block) {
   using Geo = K1Geom<T, NX>;
   constexpr int P = Geo::P, TF = Geo::TF, G = Geo::G;
   constexpr int H = R / 2;
@@ -38,7 +39,7 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
   const int tid = threadIdx.x;
   const int g = tid / TF;
   const int t = tid - g * TF;
-  const int tile = blockIdx.x * G + g;
+  const int tile = block * G + g;
   const bool active = tile < (N + 1) * L;
   const int f = active ? tile / L : 0;
   const int y1 = active ? tile - f * L : 0;
@@ -140,14 +141,43 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
   }
 }
 
+template <typename T, int NX, int R, int SB>
+__global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
+    const T* __restrict__ members, const T* __restrict__ data, int N, int ny, int L,
+    V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq, const V2<T>* __restrict__ tab) {
+  k1_body<T, NX, R, SB>(members, data, N, ny, L, ws_main, ws_nyq, tab, blockIdx.x);
+}
+
+// A batch of analyses on one grid: blockIdx.y selects the analysis.
+template <typename T, int NX, int R, int SB>
+__global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward_batch(const BatchArgs b) {
+  const BatchFilter& f = b.f[blockIdx.y];
+  k1_body<T, NX, R, SB>(static_cast<const T*>(f.members), static_cast<const T*>(f.data), b.N, b.ny, b.L,
+                        static_cast<V2<T>*>(f.ws_main), static_cast<V2<T>*>(f.ws_nyq),
+                        static_cast<const V2<T>*>(b.tab), blockIdx.x);
+}
+
+template <typename T, int NX, int R>
+constexpr int k1_sb() {
+  // sequences per LDS round: keep the (padded) buffer within 80 KB so two
+  // blocks share a CU
+  constexpr int budget = 81920 / (K1Geom<T, NX>::G * lds_padded_size(NX) * (int)sizeof(V2<T>));
+  return budget >= R / 2 ? R / 2 : budget >= 4 ? 4 : budget >= 2 ? 2 : 1;
+}
+
+template <typename T, int NX, int R>
+hipError_t launch_k1_batch_shape(const BatchArgs& b, hipStream_t st) {
+  using Geo = K1Geom<T, NX>;
+  const int tiles = (b.N + 1) * b.L;
+  const dim3 grid((tiles + Geo::G - 1) / Geo::G, b.count), block(Geo::threads);
+  hipLaunchKernelGGL((k1_forward_batch<T, NX, R, k1_sb<T, NX, R>()>), grid, block, 0, st, b);
+  return hipGetLastError();
+}
+
 template <typename T, int NX, int R>
 hipError_t launch_k1_shape(const K1Args& a, hipStream_t st) {
   using Geo = K1Geom<T, NX>;
-  constexpr int H = R / 2;
-  // sequences per LDS round: keep the (padded) buffer within 80 KB so two
-  // blocks share a CU
-  constexpr int budget = 81920 / (Geo::G * lds_padded_size(NX) * (int)sizeof(V2<T>));
-  constexpr int SB = budget >= H ? H : budget >= 4 ? 4 : budget >= 2 ? 2 : 1;
+  constexpr int SB = k1_sb<T, NX, R>();
   const int tiles = (a.N + 1) * a.L;
   const dim3 grid((tiles + Geo::G - 1) / Geo::G), block(Geo::threads);
   hipLaunchKernelGGL((k1_forward<T, NX, R, SB>), grid, block, 0, st, static_cast<const T*>(a.members),

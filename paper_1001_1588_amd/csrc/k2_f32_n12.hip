@@ -16,4 +16,19 @@ hipError_t launch_k2_f32_n12(const K2Args& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
 }
+hipError_t launch_k2_batch_f32_n12(const BatchArgs& b, hipStream_t s) {
+  switch (b.L) {
+    case 1: return launch_k2_batch_shape<float, 1, 12>(b, s);
+    case 2: return launch_k2_batch_shape<float, 2, 12>(b, s);
+    case 4: return launch_k2_batch_shape<float, 4, 12>(b, s);
+    case 8: return launch_k2_batch_shape<float, 8, 12>(b, s);
+    case 16: return launch_k2_batch_shape<float, 16, 12>(b, s);
+    case 32: return launch_k2_batch_shape<float, 32, 12>(b, s);
+    case 64: return launch_k2_batch_shape<float, 64, 12>(b, s);
+    case 128: return launch_k2_batch_shape<float, 128, 12>(b, s);
+    case 256: return launch_k2_batch_shape<float, 256, 12>(b, s);
+    case 512: return launch_k2_batch_shape<float, 512, 12>(b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 }  // namespace fftenkf

@@ -46,8 +46,9 @@ struct K2Geom {
 // SPLIT compiles the modes that start or stop at the transformed fields
 // (K2_STATS, K2_UPDATE_LEARNED, K2_INVERSE); the single-pass modes are compiled
 // without them.
+// The work of one block; `unit` is its index within one analysis.
 template <typename T, int L, int NMAX, bool SPLIT>
-__global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args a) {
+__device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   constexpr int P = k2_points(L);
   constexpr int TF2 = L / P;
   constexpr int FB = K2Geom<T>::FB;
@@ -60,7 +61,6 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
   const int tid = threadIdx.x;
   const int c = tid & (C - 1);
   const int t2 = tid / C;
-  const int unit = blockIdx.x;
   const int N = a.N, R = a.R, ny = a.ny;
   const int nxh = a.nx >> 1, nh = nxh + 1;
 
@@ -254,6 +254,38 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args
       }
     }
   }
+}
+
+template <typename T, int L, int NMAX, bool SPLIT>
+__global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args a) {
+  k2_body<T, L, NMAX, SPLIT>(a, blockIdx.x);
+}
+
+// A batch of analyses on one grid: blockIdx.y selects the analysis; b.k2 holds
+// everything the analyses share.
+template <typename T, int L, int NMAX>
+__global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral_batch(const BatchArgs b) {
+  const BatchFilter& f = b.f[blockIdx.y];
+  K2Args a = b.k2;
+  a.ws_main = f.ws_main;
+  a.ws_nyq = f.ws_nyq;
+  a.R_spec = f.R_spec;
+  a.r_scalar = f.r_scalar;
+  a.key0 = f.key0;
+  a.key1 = f.key1;
+  k2_body<T, L, NMAX, false>(a, blockIdx.x);
+}
+
+template <typename T, int L, int NMAX>
+hipError_t launch_k2_batch_shape(const BatchArgs& b, hipStream_t st) {
+  constexpr int P = k2_points(L);
+  const dim3 grid(b.k2.units_total, b.count), block(b.k2.C * (L / P));
+  constexpr size_t lds_bytes = K2Geom<T>::template lds_bytes<L>();
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_spectral_batch<T, L, NMAX>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((k2_spectral_batch<T, L, NMAX>), grid, block, lds_bytes, st, b);
+  return hipGetLastError();
 }
 
 template <typename T, int L, int NMAX, bool SPLIT>

@@ -21,10 +21,11 @@
 
 namespace fftenkf {
 
+// The work of one block; `block` is its index within one analysis.
 template <typename T, int NX, int R, int SB>
-__global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
-    const V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ ws_nyq, int N, int ny, int L, T out_scale,
-    T* __restrict__ out, const V2<T>* __restrict__ tab) {
+__device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ ws_nyq, int N,
+                                        int ny, int L, T out_scale, T* __restrict__ out,
+                                        const V2<T>* __restrict__ tab, int block) {
   using Geo = K1Geom<T, NX>;
   constexpr int P = Geo::P, TF = Geo::TF, G = Geo::G;
   constexpr int H = R / 2;
@@ -35,7 +36,7 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
   const int tid = threadIdx.x;
   const int g = tid / TF;
   const int t = tid - g * TF;
-  const int tile = blockIdx.x * G + g;
+  const int tile = block * G + g;
   const bool active = tile < N * L;
   const int f = active ? tile / L : 0;
   const int y1 = active ? tile - f * L : 0;
@@ -129,14 +130,35 @@ __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
   }
 }
 
+template <typename T, int NX, int R, int SB>
+__global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
+    const V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ ws_nyq, int N, int ny, int L, T out_scale,
+    T* __restrict__ out, const V2<T>* __restrict__ tab) {
+  k3_body<T, NX, R, SB>(ws_main, ws_nyq, N, ny, L, out_scale, out, tab, blockIdx.x);
+}
+
+// A batch of analyses on one grid: blockIdx.y selects the analysis.
+template <typename T, int NX, int R, int SB>
+__global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse_batch(const BatchArgs b) {
+  const BatchFilter& f = b.f[blockIdx.y];
+  k3_body<T, NX, R, SB>(static_cast<const V2<T>*>(f.ws_main), static_cast<const V2<T>*>(f.ws_nyq), b.N, b.ny, b.L,
+                        T(1) / (T(b.nx) * T(b.ny)), static_cast<T*>(f.out), static_cast<const V2<T>*>(b.tab),
+                        blockIdx.x);
+}
+
+template <typename T, int NX, int R>
+hipError_t launch_k3_batch_shape(const BatchArgs& b, hipStream_t st) {
+  using Geo = K1Geom<T, NX>;
+  const int tiles = b.N * b.L;
+  const dim3 grid((tiles + Geo::G - 1) / Geo::G, b.count), block(Geo::threads);
+  hipLaunchKernelGGL((k3_inverse_batch<T, NX, R, k1_sb<T, NX, R>()>), grid, block, 0, st, b);
+  return hipGetLastError();
+}
+
 template <typename T, int NX, int R>
 hipError_t launch_k3_shape(const K3Args& a, hipStream_t st) {
   using Geo = K1Geom<T, NX>;
-  constexpr int H = R / 2;
-  // sequences per LDS round: keep the (padded) buffer within 80 KB so two
-  // blocks share a CU
-  constexpr int budget = 81920 / (Geo::G * lds_padded_size(NX) * (int)sizeof(V2<T>));
-  constexpr int SB = budget >= H ? H : budget >= 4 ? 4 : budget >= 2 ? 2 : 1;
+  constexpr int SB = k1_sb<T, NX, R>();
   const int tiles = a.N * a.L;
   const dim3 grid((tiles + Geo::G - 1) / Geo::G), block(Geo::threads);
   const T out_scale = T(1) / (T(a.nx) * T(a.ny));

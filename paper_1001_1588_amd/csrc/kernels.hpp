@@ -78,6 +78,27 @@ struct K6Args {
   const void* tab;
 };
 
+// A batch of analyses with one member count, dtype and grid, run by the same
+// sweep kernels with blockIdx.y selecting the analysis.  Passed by value as a
+// kernel argument (kMaxBatch analyses per launch), so a captured graph keeps it.
+struct BatchFilter {
+  const void* members;  // [N][ny][nx]
+  const void* data;     // [ny][nx]
+  const void* R_spec;   // [ny][nx/2+1] or nullptr
+  void* out;            // [N][ny][nx]
+  void* ws_main;
+  void* ws_nyq;
+  double r_scalar;
+  uint32_t key0, key1;
+};
+constexpr int kMaxBatch = 40;
+struct BatchArgs {
+  int count, N, ny, nx, L;
+  const void* tab;
+  K2Args k2;  // the shared part of sweep 2's arguments (mode K2_ANALYZE)
+  BatchFilter f[kMaxBatch];
+};
+
 struct K3Args {
   const void* ws_main;
   const void* ws_nyq;

@@ -179,3 +179,28 @@ def test_multi_validation_and_workspace(built_lib):
     for (N, M, ny, nx, dt) in [(10, 4, 1024, 1024, 0), (3, 2, 16, 8, 1)]:
         assert lib.fftenkf_workspace_bytes_multi(N, M, ny, nx, dt) == lib.fftenkf_workspace_bytes(N * M, ny, nx, dt)
     assert lib.fftenkf_workspace_bytes_multi(4, 0, 16, 16, 0) == 0
+
+
+def test_batch_validation_and_tuning(built_lib):
+    lib = _lib.lib()
+    f = _lib.Filter(ny=16, nx=16, members=0x100000, data=0x200000, R_spec=None, out=0x300000, workspace=0x800000,
+                    workspace_bytes=1 << 20, r_scalar=0.01, seed=1)
+    arr = (_lib.Filter * 2)(f, f)
+    assert lib.fftenkf_analyze_batch(1, 0, arr, 1, None) == _lib.EINVAL         # N < 2
+    assert lib.fftenkf_analyze_batch(4, 3, arr, 1, None) == _lib.EINVAL         # dtype
+    assert lib.fftenkf_analyze_batch(25, 0, arr, 1, None) == _lib.EUNSUPPORTED
+    assert lib.fftenkf_analyze_batch(4, 0, None, 1, None) == _lib.EINVAL
+    assert lib.fftenkf_analyze_batch(4, 0, arr, 2, None) == _lib.EINVAL         # two filters write the same out
+    assert "overlaps" in lib.fftenkf_last_error().decode()
+    bad = _lib.Filter(ny=12, nx=16, members=0x100000, data=0x200000, R_spec=None, out=0x300000, workspace=0x800000,
+                      workspace_bytes=1 << 20, r_scalar=0.01, seed=1)
+    assert lib.fftenkf_analyze_batch(4, 0, (_lib.Filter * 1)(bad), 1, None) == _lib.EUNSUPPORTED
+    assert lib.fftenkf_analyze_batch(4, 0, arr, 0, None) == _lib.OK             # nothing to do
+    buf = (ctypes.c_int * 4)()
+    assert lib.fftenkf_tile_rows_options(256, 256, 0, buf, 4) == 2 and list(buf[:2]) == [8, 16]
+    assert lib.fftenkf_tile_rows_options(8, 64, 0, buf, 4) == 1 and buf[0] == 8       # R <= ny
+    assert lib.fftenkf_tile_rows_options(64, 4096, 0, buf, 4) == 1 and buf[0] == 8
+    assert lib.fftenkf_tile_rows(256, 256, 0) == 16
+    assert lib.fftenkf_set_tile_rows(256, 256, 0, 8) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 8
+    assert lib.fftenkf_set_tile_rows(256, 256, 0, 0) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 16
+    assert lib.fftenkf_set_tile_rows(256, 256, 0, 4) == _lib.EUNSUPPORTED
