@@ -12,7 +12,8 @@ duration, against 8 TB/s), and the float64 CPU oracle timed on the host.  A
 second leg times the learned spectral covariance at 2048 x 2048, N = 5 (and the
 plain analysis at the same size), with the perceptron's matrix-core rate and the
 analysis RMSE of the plain, learned and exact-covariance filters; a third times
-the multi-block analysis (4 fields of 1024 x 1024, N = 10).
+the multi-block analysis (4 fields of 1024 x 1024, N = 10); a fourth runs 256
+independent filters of uneven size, autotuned and captured in one graph.
 """
 
 from __future__ import annotations
@@ -248,6 +249,69 @@ def multiblock_leg(args, hip, dev) -> dict:
     }
 
 
+def batch_leg(args, dev) -> dict:
+    """Independent filters of uneven size in one captured graph: 256 filters with
+    sides uniform over {64, 128, 256, 512, 1024}, N = 16, float32, spectrum
+    (1+|k|^2)^-2, R = 0.01 I.  The tile schedule of each size is chosen first by
+    the autotuner; then the batch runs once eagerly, is captured, and the graph
+    replays are timed."""
+    import torch
+
+    from paper_1001_1588_amd import _lib, autotune, twin
+
+    N = 16
+    sides = twin.batch_sides(args.batch_filters, args.seed)
+    t0 = time.perf_counter()
+    table = autotune.tune([(s, s) for s in sorted(set(sides))], N, torch.float32, reps=5, device=dev)
+    tune_s = time.perf_counter() - t0
+    ens, data, seeds = [], [], []
+    for i, s in enumerate(sides):
+        e, d, sd = twin.device_twin(s, s, N, seed=args.seed * 1000 + i, r=0.01, device=dev)
+        ens.append(e)
+        data.append(d)
+        seeds.append(sd)
+    b = _lib.Batch(ens, data, [0.01] * len(sides), seeds)
+    torch.cuda.synchronize()
+
+    def timed(fn, reps):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        z.record()
+        z.synchronize()
+        return a.elapsed_time(z) / reps
+
+    eager_ms = timed(b.run, args.batch_steps)
+    b.capture()
+    graph_ms = timed(b.replay, args.batch_steps)
+    points = sum(s * s for s in sides)
+    alg = sum((2 * N + 1) * s * s * 4 for s in sides)
+    sweeps = 0
+    for s in sides:
+        bb = sweep_bytes(N, s, s, 4, False)
+        sweeps += bb["sweep1"] + bb["sweep2"] + bb["sweep3"]
+    return {
+        "workload": f"{len(sides)} independent filters, sides uniform over {{64,128,256,512,1024}} (seeded), N=16, "
+                    "float32, spectrum (1+|k|^2)^-2, R=0.01 I, one captured graph",
+        "unit": "member-gridpoints/s",
+        "value": N * points / (graph_ms * 1e-3),
+        "graph_ms_per_batch": graph_ms,
+        "eager_ms_per_batch": eager_ms,
+        "steps": args.batch_steps,
+        "filters_per_side": {str(s): sides.count(s) for s in sorted(set(sides))},
+        "member_gridpoints": N * points,
+        "path_bytes": alg,
+        "path_hbm_frac": alg / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "sweep_bytes": sweeps,
+        "sweep_bytes_hbm_frac": sweeps / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "tile_rows": {k: v["rows"] for k, v in table.items()},
+        "autotune": {"seconds": tune_s, "ms_per_analysis": {k: v["ms"] for k, v in table.items()}},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +321,8 @@ def main() -> int:
     ap.add_argument("--cpu-members", type=int, default=20, help="members in the CPU oracle sample (0 = skip)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the device copy ceiling probe (0 = skip)")
+    ap.add_argument("--batch-filters", type=int, default=256, help="filters of the batched leg (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--multi-steps", type=int, default=20,
                     help="timed analyses of the multi-block leg (0 = skip)")
     ap.add_argument("--learned-steps", type=int, default=20,
@@ -355,6 +421,8 @@ def main() -> int:
         result["learned_covariance"] = learned_leg(args, hip, dev)
     if args.multi_steps > 0:
         result["multiblock"] = multiblock_leg(args, hip, dev)
+    if args.batch_filters > 0:
+        result["batch"] = batch_leg(args, dev)
     if args.cpu_members > 0:
         result["cpu_baseline"] = cpu_baseline(tw, min(args.cpu_members, N))
     print(json.dumps(result), flush=True)

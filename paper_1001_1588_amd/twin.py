@@ -17,6 +17,10 @@ WRF-Fire ideal problem, Section 4):
   d = truth + N(0, 0.01 I), R = 0.01 I.
 * ``large2048`` -- periodic 2048x2048, float32, N=20, lambda = |k|^-3 (k != 0),
   lambda(0) = 0, d = truth + N(0, 0.05 I), R = 0.05 I.
+* batch (``batch_sides`` + ``device_twin``) -- 256 independent filters, square
+  sides drawn uniformly from {64, 128, 256, 512, 1024}, float32, N=16, lambda =
+  (1+|k|^2)^-2, R = 0.01 I; drawn on the device with torch (same law as
+  ``make_twin``) because numpy would take minutes at that size.
 * multi-block (``make_multiblock_twin``) -- 4 fields of 1024x1024, float32,
   N=10, lambda_b = (1 + |k|^2 / L_b^2)^-2 with L_b in {8, 16, 32, 64}, spectral
   coherence 0.6 between blocks through a shared latent field, d observes block
@@ -195,3 +199,32 @@ def make_multiblock_twin(ny: int, nx: int, N: int, *, seed: int, Ls=(8.0, 16.0, 
     R_spec = np.full((ny, nx // 2 + 1), r, dtype=np.float64)
     return MultiTwin(ens=ens.astype(dtype), data=data.astype(dtype), R_spec=R_spec.astype(dtype), r=r,
                      seed=an_seed, truth=truth.astype(dtype), lam=lams, rho=rho)
+
+
+def batch_sides(n_filters: int, seed: int, choices=(64, 128, 256, 512, 1024)) -> list:
+    """Square grid sides of a batch of independent filters, uniform over `choices`."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 4]))
+    return [int(c) for c in rng.choice(np.asarray(choices), size=n_filters)]
+
+
+def device_twin(ny: int, nx: int, N: int, *, seed: int, r: float = 0.01, kind: str = "matern2", kw=None,
+                device="cuda:0"):
+    """A twin like make_twin (members = truth + draws, d = truth + N(0, r I)),
+    float32, drawn on the device with torch's generator; returns (ens, data,
+    analysis seed).  The fields are white noise filtered by sqrt(lambda) in the
+    unitary Fourier basis, as gaussian_fields does."""
+    import torch
+
+    kw = kw or {}
+    g = torch.Generator(device=device).manual_seed(seed)
+    amp = torch.from_numpy(np.sqrt(spectrum(ny, nx, kind, **kw)[:, : nx // 2 + 1])).to(device, torch.float32)
+
+    def fields(count):
+        w = torch.randn((count, ny, nx), generator=g, device=device, dtype=torch.float32)
+        return torch.fft.irfft2(torch.fft.rfft2(w, norm="ortho") * amp, s=(ny, nx), norm="ortho")
+
+    truth = fields(1)[0]
+    ens = (truth[None] + fields(N)).contiguous()
+    data = (truth + np.sqrt(r) * torch.randn((ny, nx), generator=g, device=device, dtype=torch.float32)).contiguous()
+    an_seed = int(torch.randint(0, 2**62, (1,), generator=g, device=device).item())
+    return ens, data, an_seed

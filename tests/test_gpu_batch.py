@@ -113,3 +113,35 @@ def test_tile_rows_change_rounding_only():
         assert rel_l2(o, ref) <= 1e-5
     with pytest.raises(RuntimeError):
         _lib.set_tile_rows(256, 256, torch.float32, 32)
+
+
+def test_autotuner_sets_a_compiled_choice():
+    from paper_1001_1588_amd import autotune
+    grids = [(128, 128), (64, 256)]
+    try:
+        table = autotune.tune(grids, 8, torch.float32, reps=3)
+        for ny, nx in grids:
+            rec = table[autotune.key(ny, nx, torch.float32)]
+            assert rec["rows"] in _lib.tile_rows_options(ny, nx, torch.float32)
+            assert _lib.tile_rows(ny, nx, torch.float32) == rec["rows"]
+            assert all(t > 0 for t in rec["ms"].values())
+    finally:
+        for ny, nx in grids:
+            _lib.set_tile_rows(ny, nx, torch.float32, 0)
+
+
+def test_device_twin_statistics():
+    """The device generator of the batched workload draws the stated law."""
+    ens, data, seed = twin.device_twin(128, 128, 16, seed=4, r=0.01, device=DEV)
+    lam = twin.spectrum(128, 128, "matern2")[:, :65]
+    dev_ = ens - ens.mean(dim=0, keepdim=True)
+    c = (torch.fft.rfft2(dev_.double(), norm="ortho").abs() ** 2).sum(dim=0) / 15
+    ratio = float((c.cpu().numpy() / lam).mean())
+    assert abs(ratio - 1) < 0.02
+    # data = truth + N(0, r I): at high wavenumbers the fields carry almost no
+    # power, so d - mean(ens) has the unitary power r of the white noise there
+    resid = torch.fft.rfft2((data - ens.mean(dim=0)).double(), norm="ortho").abs() ** 2
+    ky = torch.minimum(torch.arange(128), 128 - torch.arange(128))[:, None].double()
+    kx = torch.arange(65)[None, :].double()
+    high = ((ky ** 2 + kx ** 2) > 40 ** 2).to(DEV)
+    assert abs(float(resid[high].mean()) / 0.01 - 1) < 0.05

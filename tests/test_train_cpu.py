@@ -78,3 +78,23 @@ def test_tiny_training_run(tmp_path):
         assert d[k].shape == shape and d[k].dtype == np.float32
     meta = json.loads(str(d["meta"]))
     assert meta["members"] == 5 and np.isfinite(meta["val_mse_bf16"])
+
+
+def test_autotune_pick_and_table_roundtrip(tmp_path, monkeypatch):
+    from paper_1001_1588_amd import autotune
+    assert autotune.pick({8: 1.0, 16: 0.5}) == 16
+    assert autotune.pick({8: 0.5, 16: 0.5}) == 8           # ties: fewer rows
+    calls = []
+    monkeypatch.setattr(autotune._lib, "set_tile_rows", lambda ny, nx, dt, r: calls.append((ny, nx, dt, r)))
+    table = {"256x256:float32": {"rows": 8}, "64x4096:float64": {"rows": 4}}
+    p = tmp_path / "t.json"
+    p.write_text(__import__("json").dumps(table))
+    autotune.load(str(p))
+    assert calls == [(256, 256, torch.float32, 8), (64, 4096, torch.float64, 4)]
+
+
+def test_batch_sides_are_seeded_and_uniform():
+    a = twin.batch_sides(256, 1)
+    assert a == twin.batch_sides(256, 1) and a != twin.batch_sides(256, 2)
+    assert set(a) == {64, 128, 256, 512, 1024}
+    assert all(20 < a.count(s) < 85 for s in set(a))
