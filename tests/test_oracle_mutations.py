@@ -15,7 +15,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["test_oracle_dft.py", "test_oracle_variance.py", "test_oracle_update.py", "test_oracle_rng.py",
-             "test_oracle_learned.py", "test_oracle_multiblock.py"]
+             "test_oracle_learned.py", "test_oracle_multiblock.py", "test_oracle_dst.py"]
 
 MUTANTS = [
     ("enkf.py", "sum(axis=0) / (N - 1)", "sum(axis=0) / N"),
@@ -41,6 +41,10 @@ MUTANTS = [
     ("multiblock.py", "np.roll(a, (-hy, -hx), axis=(1, 2)) * b", "np.roll(a, (hy, hx), axis=(1, 2)) * b"),
     ("multiblock.py", "G = np.where(den < tiny, 0.0, cj1 / np.where(den < tiny, 1.0, den))",
      "G = np.where(den < tiny, 0.0, cj1 / np.where(den < tiny, 1.0, c11))"),
+    ("dst.py", "    S[n - 1] /= np.sqrt(2.0)\n", "\n"),
+    ("dst.py", "(2 * j + 1) * (k + 1) / (2 * n)", "(2 * j + 1) * k / (2 * n)"),
+    ("dst.py", "((s_hat - mean) ** 2).sum(axis=0) / (N - 1)", "((s_hat - mean) ** 2).sum(axis=0) / N"),
+    ("dst.py", "return dst2_matrix(ny).T @ s @ dst2_matrix(nx)", "return dst2_matrix(ny) @ s @ dst2_matrix(nx).T"),
     ("learned.py", "full[:, kx] = c_half[ky, nx - kx]", "full[:, kx] = c_half[:, nx - kx]"),
     ("learned.py", "dy, dx = j // 5 - 2, j % 5 - 2", "dx, dy = j // 5 - 2, j % 5 - 2"),
     ("learned.py", "np.log(full / mu + EPS)", "np.log(full + EPS)"),
