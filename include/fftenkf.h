@@ -203,6 +203,32 @@ int fftenkf_tile_rows_options(int ny, int nx, int dtype, int* rows, int capacity
 int fftenkf_set_tile_rows(int ny, int nx, int dtype, int rows);
 int fftenkf_tile_rows(int ny, int nx, int dtype);
 
+/*
+ * The analysis in the real sine basis (Section 4: the sine transform forces
+ * zero change on the boundary).  The transform is the orthonormal 2D DST-II,
+ *   S[k][j] = sqrt(2/n) c_k sin(pi (2j + 1)(k + 1) / (2n)),  c_{n-1} = 1/sqrt(2), else 1,
+ * per axis, whose basis functions vanish at the cell faces j = -1/2, n - 1/2;
+ * eq. (2) and eq. (3) act on its real coefficients:
+ *   c_hat = 1/(N-1) sum_k (s_hat_k - mean)^2,
+ *   s_hat_k^a = s_hat_k + c_hat / (c_hat + R_dst) (d_hat + e_hat_k - s_hat_k),
+ * and the analysis is S^T s_hat_k^a.  e_hat_k = sqrt(R_dst) z with z the first
+ * output of Box-Muller on words (x0, x1) of Philox4x32-10 for even k, (x2, x3)
+ * for odd k, key as for fftenkf_analyze, counter = (s1 * nx + s2, k div 2, 1, 0)
+ * for the sine bin (s1, s2).
+ *   R_dst : device [ny][nx] real, the eigenvalues of R in the sine basis (>= 0),
+ *           or NULL to use ens->r_scalar;
+ *   workspace : fftenkf_workspace_bytes_dst(N, ny, nx, dtype) bytes.
+ * Other arguments and rules as for fftenkf_analyze (same N limits).
+ */
+int fftenkf_analyze_dst(const fftenkf_ens* ens, const void* data, const void* R_dst, uint64_t seed, void* out);
+
+/* Workspace bytes of fftenkf_analyze_dst and fftenkf_debug_dst_coeffs; 0 if invalid. */
+size_t fftenkf_workspace_bytes_dst(int n_members, int ny, int nx, int dtype);
+
+/* Test-only: the orthonormal sine coefficients [N+1][ny][nx] (members, then
+ * data) that fftenkf_analyze_dst works on, into device `coeffs`. */
+int fftenkf_debug_dst_coeffs(const fftenkf_ens* ens, const void* data, void* coeffs);
+
 /* Releases cached library state.  The library keeps only its twiddle tables,
  * which are static device arrays filled on first use and live until the
  * process ends, so there is nothing to free: returns FFTENKF_OK. */

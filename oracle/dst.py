@@ -39,17 +39,24 @@ def dst2_matrix(n: int) -> np.ndarray:
     return S
 
 
-def dst2(u: np.ndarray) -> np.ndarray:
-    """Orthonormal 2D DST-II of real fields [..., ny, nx]."""
+def dst2(u: np.ndarray, method: str = "matmul") -> np.ndarray:
+    """Orthonormal 2D DST-II of real fields [..., ny, nx]; method "fft" is the
+    same transform by scipy.fft (for large grids; pinned against the matrices)."""
     u = np.asarray(u, dtype=np.float64)
     ny, nx = u.shape[-2:]
+    if method == "fft":
+        import scipy.fft as sf
+        return sf.dstn(u, type=2, norm="ortho", axes=(-2, -1))
     return dst2_matrix(ny) @ u @ dst2_matrix(nx).T
 
 
-def idst2(s: np.ndarray) -> np.ndarray:
+def idst2(s: np.ndarray, method: str = "matmul") -> np.ndarray:
     """Inverse of dst2 (the transpose: the matrices are orthogonal)."""
     s = np.asarray(s, dtype=np.float64)
     ny, nx = s.shape[-2:]
+    if method == "fft":
+        import scipy.fft as sf
+        return sf.idstn(s, type=2, norm="ortho", axes=(-2, -1))
     return dst2_matrix(ny).T @ s @ dst2_matrix(nx)
 
 
@@ -65,21 +72,21 @@ def dst_noise(seed: int, N: int, ny: int, nx: int) -> np.ndarray:
     return z.reshape(N, ny, nx)
 
 
-def analyze_dst(ens, data, R_dst, seed: int, *, tiny=None, return_parts: bool = False):
+def analyze_dst(ens, data, R_dst, seed: int, *, tiny=None, return_parts: bool = False, method: str = "matmul"):
     """Eq. (2)-(3) in the sine basis, with the seeded real perturbations."""
     ens = np.asarray(ens)
     N, ny, nx = ens.shape
     if tiny is None:
         tiny = tiny_for(ens.dtype)
     R_dst = np.broadcast_to(np.asarray(R_dst, dtype=np.float64), (ny, nx))
-    s_hat = dst2(ens.astype(np.float64))
-    d_hat = dst2(np.asarray(data, dtype=np.float64))
+    s_hat = dst2(ens.astype(np.float64), method)
+    d_hat = dst2(np.asarray(data, dtype=np.float64), method)
     mean = s_hat.mean(axis=0)
     c_hat = ((s_hat - mean) ** 2).sum(axis=0) / (N - 1)
     K = spectral_gain(c_hat, R_dst, tiny)
     e_hat = np.sqrt(R_dst)[None] * dst_noise(seed, N, ny, nx)
     sa = s_hat + K[None] * (d_hat[None] + e_hat - s_hat)
-    ua = idst2(sa)
+    ua = idst2(sa, method)
     if return_parts:
         return ua, dict(s_hat=s_hat, d_hat=d_hat, c_hat=c_hat, K=K, e_hat=e_hat)
     return ua

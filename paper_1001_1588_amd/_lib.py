@@ -80,6 +80,10 @@ EXPORTS = {
     "fftenkf_analyze_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                                 ctypes.c_void_p, ctypes.c_void_p]),
     "fftenkf_release_caches": (ctypes.c_int, []),
+    "fftenkf_analyze_dst": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                           ctypes.c_void_p]),
+    "fftenkf_workspace_bytes_dst": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "fftenkf_debug_dst_coeffs": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p]),
     "fftenkf_analyze_batch": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Filter), ctypes.c_int,
                                              ctypes.c_void_p]),
     "fftenkf_tile_rows_options": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -197,6 +201,42 @@ def analyze_multi(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Ten
     st = lib().fftenkf_analyze_multi(ctypes.byref(e), M, data.data_ptr(), _ptr(R_t),
                                      ctypes.c_uint64(seed & (2**64 - 1)), out.data_ptr())
     _check(st, "fftenkf_analyze_multi")
+    return out
+
+
+def _dst_ens(ens: torch.Tensor, workspace: Optional[torch.Tensor], r_scalar: float):
+    if ens.dim() != 3 or not ens.is_cuda or not ens.is_contiguous():
+        raise ValueError("ens must be a contiguous device tensor [N, ny, nx]")
+    N, ny, nx = ens.shape
+    code = _dtype_code(ens)
+    if workspace is None:
+        need = int(lib().fftenkf_workspace_bytes_dst(N, ny, nx, code))
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=ens.device)
+    e = Ens(n_members=N, ny=ny, nx=nx, dtype=code, members=ens.data_ptr(), workspace=workspace.data_ptr(),
+            workspace_bytes=workspace.numel(), stream=torch.cuda.current_stream(ens.device).cuda_stream,
+            r_scalar=float(r_scalar))
+    return e, workspace
+
+
+def analyze_dst(ens: torch.Tensor, data: torch.Tensor, R_dst: Union[torch.Tensor, float], seed: int,
+                out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The analysis in the real sine basis: R_dst [ny, nx] (eigenvalues of R in that basis) or a float r."""
+    R_t, r = _rspec(R_dst)
+    e, ws = _dst_ens(ens, workspace, r)
+    if out is None:
+        out = torch.empty_like(ens)
+    st = lib().fftenkf_analyze_dst(ctypes.byref(e), data.data_ptr(), _ptr(R_t), ctypes.c_uint64(seed & (2**64 - 1)),
+                                   out.data_ptr())
+    _check(st, "fftenkf_analyze_dst")
+    return out
+
+
+def debug_dst_coeffs(ens: torch.Tensor, data: torch.Tensor) -> torch.Tensor:
+    """Orthonormal sine coefficients [N+1, ny, nx] of the members and d."""
+    e, ws = _dst_ens(ens, None, 0.0)
+    N, ny, nx = ens.shape
+    out = torch.empty((N + 1, ny, nx), dtype=ens.dtype, device=ens.device)
+    _check(lib().fftenkf_debug_dst_coeffs(ctypes.byref(e), data.data_ptr(), out.data_ptr()), "fftenkf_debug_dst_coeffs")
     return out
 
 

@@ -611,6 +611,68 @@ int run_batch(int N, int dtype, const fftenkf_filter* fs, int n, const std::vect
   return FFTENKF_OK;
 }
 
+// Workspace of the sine-basis analysis: the spectral workspace, then the
+// reordered fields v of Makhoul's form ((N+1) planes of ny * nx reals).
+size_t dst_ws_bytes(const Plan& plan, int N, int ny, int nx, int dtype) {
+  return round256(plan.ws_bytes + (size_t)(N + 1) * ny * nx * dsize(dtype));
+}
+
+// pre (x -> v), sweep 1, the statistics mode of sweep 2, the per-bin sine-basis
+// kernel, then (for an analysis) the inverse-only mode of sweep 2, sweep 3 and
+// post (v -> x).
+int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_dst, uint64_t seed, void* out,
+            void* dbg_coeffs) {
+  if (t_fail_next != 0) {
+    const int st = t_fail_next;
+    t_fail_next = 0;
+    return fail(st, "failure forced by fftenkf_debug_fail_next");
+  }
+  hipStream_t stream = static_cast<hipStream_t>(e->stream);
+  const void* tab = nullptr;
+  hipError_t err = twiddle_table(e->dtype, &tab);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
+  char* ws = static_cast<char*>(e->workspace);
+  void* ws_main = ws;
+  void* ws_nyq = ws + plan.off_nyq;
+  char* v = ws + plan.ws_bytes;
+  const int N = e->n_members, ny = e->ny, nx = e->nx;
+  const size_t field = (size_t)ny * nx * dsize(e->dtype);
+  err = launch_dst_pre(e->members, data, N, ny, nx, v, e->dtype, stream);
+  K1Args a1{v, v + (size_t)N * field, N, ny, nx, plan.R, plan.L, ws_main, ws_nyq, tab};
+  if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
+  K2Args a2{};
+  a2.ws_main = ws_main;
+  a2.ws_nyq = ws_nyq;
+  a2.r_scalar = 1.0;
+  a2.N = N;
+  a2.ny = ny;
+  a2.nx = nx;
+  a2.R = plan.R;
+  a2.L = plan.L;
+  a2.C = plan.C;
+  a2.units_main = plan.units_main;
+  a2.units_total = plan.units_total;
+  a2.group_xcd = plan.group_xcd;
+  a2.chat_map = ws + plan.off_chat;
+  a2.partials = ws + plan.off_part;
+  a2.tab = tab;
+  a2.mode = K2_STATS;
+  auto k2 = [&]() { return e->dtype == FFTENKF_F32 ? launch_k2_f32(a2, stream) : launch_k2_f64(a2, stream); };
+  if (err == hipSuccess) err = k2();
+  K9Args a9{ws_main, ws_nyq, R_dst, e->r_scalar, N, ny, nx, plan.R, plan.L,
+            (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), dbg_coeffs};
+  if (err == hipSuccess) err = launch_dst_quad(a9, e->dtype, stream);
+  if (err == hipSuccess && dbg_coeffs == nullptr) {
+    a2.mode = K2_INVERSE;
+    err = k2();
+    K3Args a3{ws_main, ws_nyq, N, ny, nx, plan.R, plan.L, v, tab};
+    if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
+    if (err == hipSuccess) err = launch_dst_post(v, N, ny, nx, out, e->dtype, stream);
+  }
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sine-basis analysis launch: %s", hipGetErrorString(err));
+  return FFTENKF_OK;
+}
+
 // The eight weight arrays of the perceptron: present and aligned (host-side
 // checks), then device memory of the current device.
 int check_mlp(const fftenkf_mlp* m, bool device) {
@@ -979,6 +1041,83 @@ int fftenkf_analyze_batch(int n_members, int dtype, const fftenkf_filter* filter
                                  static_cast<hipStream_t>(stream), "R_spec");
     if (st != FFTENKF_OK) return st;
     return run_batch(n_members, dtype, filters, n_filters, plans, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+size_t fftenkf_workspace_bytes_dst(int n_members, int ny, int nx, int dtype) {
+  if ((dtype != FFTENKF_F32 && dtype != FFTENKF_F64) || n_members < 2 || !pow2_in_range(ny) || !pow2_in_range(nx))
+    return 0;
+  return dst_ws_bytes(make_plan(n_members, ny, nx, dtype), n_members, ny, nx, dtype);
+}
+
+// Shared checks of the sine-basis entry points; the workspace includes the v planes.
+int validate_dst(const fftenkf_ens* e, Plan* plan) {
+  fftenkf_ens copy = *e;
+  copy.workspace_bytes = (size_t)-1;  // checked below against the larger size
+  int st = validate_shape(&copy, plan);
+  if (st != FFTENKF_OK) return st;
+  const size_t need = dst_ws_bytes(*plan, e->n_members, e->ny, e->nx, e->dtype);
+  if (e->workspace_bytes < need) return fail(FFTENKF_EINVAL, "workspace of %zu bytes, %zu needed", e->workspace_bytes, need);
+  return FFTENKF_OK;
+}
+
+int fftenkf_analyze_dst(const fftenkf_ens* e, const void* data, const void* R_dst, uint64_t seed, void* out) {
+  try {
+    if (e == nullptr) return fail(FFTENKF_EINVAL, "ens is NULL");
+    Plan plan;
+    int st = validate_dst(e, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (data == nullptr || out == nullptr) return fail(FFTENKF_EINVAL, "data and out are required");
+    if (misaligned(data, 16) || misaligned(out, 16) || (R_dst != nullptr && misaligned(R_dst, 16)))
+      return fail(FFTENKF_EINVAL, "data, R_dst and out must be 16-byte aligned");
+    if (R_dst == nullptr && !(e->r_scalar >= 0.0)) return fail(FFTENKF_EINVAL, "r_scalar must be >= 0 when R_dst is NULL");
+    const size_t s = dsize(e->dtype);
+    const size_t field = (size_t)e->ny * e->nx * s;
+    const size_t ens_b = field * e->n_members;
+    const size_t ws_b = dst_ws_bytes(plan, e->n_members, e->ny, e->nx, e->dtype);
+    const Ptr ptrs[] = {{e->members, ens_b, "members"},
+                        {data, field, "data"},
+                        {R_dst, field, "R_dst"},
+                        {out, ens_b, "out"},
+                        {e->workspace, ws_b, "workspace"}};
+    for (int i = 0; i < 5; ++i)
+      for (int j = i + 1; j < 5; ++j) {
+        if (ptrs[i].p == nullptr || ptrs[j].p == nullptr) continue;
+        const bool in_place = (i == 0 && j == 3 && ptrs[i].p == ptrs[j].p);
+        if (!in_place && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+      }
+    st = check_pointers(ptrs, 5);
+    if (st == FFTENKF_OK)
+      st = check_spectrum_values(R_dst, (size_t)e->ny * e->nx, e->dtype, static_cast<hipStream_t>(e->stream), "R_dst");
+    if (st != FFTENKF_OK) return st;
+    return run_dst(e, plan, data, R_dst, seed, out, nullptr);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+int fftenkf_debug_dst_coeffs(const fftenkf_ens* e, const void* data, void* coeffs) {
+  try {
+    if (e == nullptr) return fail(FFTENKF_EINVAL, "ens is NULL");
+    Plan plan;
+    int st = validate_dst(e, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (data == nullptr || coeffs == nullptr) return fail(FFTENKF_EINVAL, "data and coeffs are required");
+    const size_t field = (size_t)e->ny * e->nx * dsize(e->dtype);
+    const Ptr ptrs[] = {{e->members, field * e->n_members, "members"},
+                        {data, field, "data"},
+                        {coeffs, field * (e->n_members + 1), "coeffs"},
+                        {e->workspace, dst_ws_bytes(plan, e->n_members, e->ny, e->nx, e->dtype), "workspace"}};
+    for (int i = 0; i < 4; ++i)
+      for (int j = i + 1; j < 4; ++j)
+        if (overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+    st = check_pointers(ptrs, 4);
+    if (st != FFTENKF_OK) return st;
+    return run_dst(e, plan, data, nullptr, 0, nullptr, coeffs);
   } catch (...) {
     return fail(FFTENKF_EDEVICE, "internal error");
   }

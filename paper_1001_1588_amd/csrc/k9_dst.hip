@@ -1,0 +1,256 @@
+// The analysis in the real sine basis (Section 4): orthonormal 2D DST-II
+// coefficients through the 2D FFT of the analysis, by Makhoul's reordering.
+//
+// With y(j1, j2) = (-1)^(j1 + j2) x(j1, j2), the DST-II of x at (s1, s2) is the
+// DCT-II of y at (n1-1-s1, n2-1-s2).  With v(j1, j2) = y(rho1(j1), rho2(j2)),
+// rho(j) = 2j for j < n/2 and 2(n-1-j)+1 above, and V its unnormalised 2D DFT,
+//   X(k1, k2) = 1/2 Re[ W1(k1) (W2(k2) V(k1, k2) + conj W2(k2) V(k1, -k2)) ],
+//   W(k) = exp(-i pi k / (2n)),
+// is the unnormalised DCT-II of y, and conversely
+//   V(k1, k2) = conj(W1(k1) W2(k2)) [ X(k1, k2) - X(n1-k1, n2-k2) - i (X(n1-k1, k2) + X(k1, n2-k2)) ]
+// with X = 0 at index n.  The orthonormal coefficient is alpha1(k1) alpha2(k2)
+// X(k1, k2), alpha(0) = sqrt(1/n), alpha(k > 0) = sqrt(2/n).
+//
+// Launches: dst_pre (x -> v for the members and d), sweep 1 and the statistics
+// mode of sweep 2 (V left in the workspace), dst_quad (per mirror set of bins:
+// V -> X -> eq. (2)-(3) in the sine basis -> X^a -> V^a), the inverse-only mode
+// of sweep 2 and sweep 3 (V^a -> v^a), dst_post (v^a -> x^a).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "fft_core.hpp"
+#include "kernels.hpp"
+#include "philox.hpp"
+
+namespace fftenkf {
+
+namespace {
+
+__device__ __forceinline__ int rho(int j, int n) { return j < n / 2 ? 2 * j : 2 * (n - 1 - j) + 1; }
+__device__ __forceinline__ int rho_inv(int i, int n) { return (i & 1) ? n - 1 - (i >> 1) : (i >> 1); }
+
+template <typename T> __device__ __forceinline__ void sincospi_t(T x, T* s, T* c);
+template <> __device__ __forceinline__ void sincospi_t<float>(float x, float* s, float* c) { sincospif(x, s, c); }
+template <> __device__ __forceinline__ void sincospi_t<double>(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// W(k) = exp(-i pi k / (2n))
+template <typename T>
+__device__ __forceinline__ cx<T> wq(int k, int n) {
+  T s, c;
+  sincospi_t<T>(T(k) / T(2 * n), &s, &c);
+  return cx<T>{c, -s};
+}
+
+template <typename T> __device__ __forceinline__ T tiny_t();
+template <> __device__ __forceinline__ float tiny_t<float>() { return 1.17549435e-38f; }
+template <> __device__ __forceinline__ double tiny_t<double>() { return 2.2250738585072014e-308; }
+
+// v(j1, j2) = (-1)^(i1 + i2) x(i1, i2), (i1, i2) = (rho(j1), rho(j2)), for the
+// N members and d (field N); one thread per output element.
+template <typename T>
+__global__ void dst_pre(const T* __restrict__ members, const T* __restrict__ data, int N, int ny, int nx,
+                        T* __restrict__ v) {
+  const size_t n = (size_t)ny * nx;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)(N + 1) * n) return;
+  const int f = (int)(idx / n);
+  const size_t e = idx - (size_t)f * n;
+  const int j1 = (int)(e / nx), j2 = (int)(e - (size_t)j1 * nx);
+  const int i1 = rho(j1, ny), i2 = rho(j2, nx);
+  const T* src = f < N ? members + (size_t)f * n : data;
+  const T x = src[(size_t)i1 * nx + i2];
+  v[idx] = ((i1 + i2) & 1) ? -x : x;
+}
+
+// x(i1, i2) = (-1)^(i1 + i2) v(rho^-1(i1), rho^-1(i2)) for the N members.
+template <typename T>
+__global__ void dst_post(const T* __restrict__ v, int N, int ny, int nx, T* __restrict__ out) {
+  const size_t n = (size_t)ny * nx;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)N * n) return;
+  const int f = (int)(idx / n);
+  const size_t e = idx - (size_t)f * n;
+  const int i1 = (int)(e / nx), i2 = (int)(e - (size_t)i1 * nx);
+  const T y = v[(size_t)f * n + (size_t)rho_inv(i1, ny) * nx + rho_inv(i2, nx)];
+  out[idx] = ((i1 + i2) & 1) ? -y : y;
+}
+
+template <typename T>
+__device__ __forceinline__ V2<T>* spectrum_at(const K9Args& a, int f, int ky, int kx) {
+  const int nxh = a.nx / 2;
+  const int k2 = ky % a.R, k1 = ky / a.R;
+  if (kx < nxh) return static_cast<V2<T>*>(a.ws_main) + (((size_t)f * a.R + k2) * a.L + k1) * nxh + kx;
+  return static_cast<V2<T>*>(a.ws_nyq) + ((size_t)f * a.L + k1) * a.R + k2;
+}
+
+// One thread per mirror set {a, n1-a} x {b, n2-b}, 0 <= a <= n1/2, 0 <= b <= n2/2.
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void dst_quad(const K9Args a) {
+  const int n1 = a.ny, n2 = a.nx;
+  const int hb = n2 / 2 + 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (n1 / 2 + 1) * hb) return;
+  const int qa = idx / hb, qb = idx - qa * hb;
+  const int ma = (n1 - qa) % n1, mb = (n2 - qb) % n2;  // the mirror rows and columns
+  const bool da = ma != qa, db = mb != qb;             // distinct mirror point
+  const int N = a.N;
+  // the four points: 0 (qa, qb), 1 (ma, qb), 2 (qa, mb), 3 (ma, mb)
+  const int pk1[4] = {qa, ma, qa, ma}, pk2[4] = {qb, qb, mb, mb};
+  cx<T> W1[4], W2[4];
+  T alpha[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    W1[p] = wq<T>(pk1[p], n1);
+    W2[p] = wq<T>(pk2[p], n2);
+    alpha[p] = sqrt((pk1[p] == 0 ? T(1) : T(2)) / T(n1)) * sqrt((pk2[p] == 0 ? T(1) : T(2)) / T(n2));
+  }
+  // X of every field at the four points (orthonormal sine coefficients)
+  // (member k in row k, d in row NMAX; padding rows are never read)
+  T s[NMAX + 1][4];
+#pragma unroll
+  for (int f = 0; f <= NMAX; ++f) {
+    if (f < N || f == NMAX) {
+      const int field = f == NMAX ? N : f;
+      const cx<T> Vab = from2<T>(*spectrum_at<T>(a, field, qa, qb));
+      const cx<T> Vmb = from2<T>(*spectrum_at<T>(a, field, ma, qb));
+      // V at (qa, -qb) = conj V(ma, qb); at (ma, -qb) = conj V(qa, qb)
+      const cx<T> Vp[4] = {Vab, Vmb, conj(Vmb), conj(Vab)};
+      const cx<T> Vn[4] = {conj(Vmb), conj(Vab), Vab, Vmb};  // V at (k1, -k2) of each point
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const cx<T> z = W1[p] * (W2[p] * Vp[p] + conj(W2[p]) * Vn[p]);
+        s[f][p] = T(0.5) * z.re * alpha[p];
+      }
+    }
+  }
+  // eq. (2)-(3) at each distinct point; the DST bin is (n1-1-k1, n2-1-k2)
+  const bool live[4] = {true, da, db, da && db};
+  const T* __restrict__ Rd = static_cast<const T*>(a.R_dst);
+  static_for<0, 4>([&](auto PI) __attribute__((always_inline)) {
+    constexpr int p = decltype(PI)::value;
+    if (!live[p]) return;
+    const int s1 = n1 - 1 - pk1[p], s2 = n2 - 1 - pk2[p];
+    T mean = T(0);
+#pragma unroll
+    for (int f = 0; f < NMAX; ++f)
+      if (f < N) mean += s[f][p];
+    mean /= T(N);
+    T var = T(0);
+#pragma unroll
+    for (int f = 0; f < NMAX; ++f)
+      if (f < N) var += (s[f][p] - mean) * (s[f][p] - mean);
+    const T c = var / T(N - 1);
+    const T r = Rd != nullptr ? Rd[(size_t)s1 * n2 + s2] : T(a.r_scalar);
+    const T den = c + r;
+    const T gain = den < tiny_t<T>() ? T(0) : c / den;
+    const T amp = sqrt(r);
+    if (a.dbg_coeffs != nullptr) {  // test export: the sine coefficients of every field
+      T* dc = static_cast<T*>(a.dbg_coeffs);
+      const size_t plane = (size_t)n1 * n2, bin = (size_t)s1 * n2 + s2;
+#pragma unroll
+      for (int f = 0; f < NMAX; ++f)
+        if (f < N) dc[f * plane + bin] = s[f][p];
+      dc[N * plane + bin] = s[NMAX][p];
+      return;
+    }
+    const uint32_t ctr0 = (uint32_t)(s1 * n2 + s2);
+#pragma unroll
+    for (int q = 0; q < (NMAX + 1) / 2; ++q) {
+      if (2 * q < N) {
+        const u32x4 w = philox4x32_10(u32x4{ctr0, (uint32_t)q, 1u, 0u}, a.key0, a.key1);
+        T za, zb;
+        box_muller<T>(w.x0, w.x1, za, zb);
+        s[2 * q][p] += gain * (s[NMAX][p] + amp * za - s[2 * q][p]);
+        if (2 * q + 1 < NMAX && 2 * q + 1 < N) {
+          box_muller<T>(w.x2, w.x3, za, zb);
+          s[2 * q + 1][p] += gain * (s[NMAX][p] + amp * za - s[2 * q + 1][p]);
+        }
+      }
+    }
+  });
+  if (a.dbg_coeffs != nullptr) return;
+  // back to V at the two stored points (qa, qb) and (ma, qb); a mirror point
+  // that coincides with another holds that point's updated value
+#pragma unroll
+  for (int f = 0; f < NMAX; ++f) {
+    if (f >= N) continue;
+    T X[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) X[p] = s[f][p] / alpha[p];
+    if (!da) {
+      X[1] = X[0];
+      X[3] = X[2];
+    }
+    if (!db) {
+      X[2] = X[0];
+      X[3] = X[1];
+    }
+    // X at index n (a mirror of row or column 0) is zero
+    const T x_ab = X[0];
+    const T x_mr = qa == 0 ? T(0) : X[1];              // X(n1 - qa, qb)
+    const T x_mc = qb == 0 ? T(0) : X[2];              // X(qa, n2 - qb)
+    const T x_mm = (qa == 0 || qb == 0) ? T(0) : X[3];  // X(n1 - qa, n2 - qb)
+    const cx<T> Va = conj(W1[0] * W2[0]) * cx<T>{x_ab - x_mm, -(x_mr + x_mc)};
+    *spectrum_at<T>(a, f, qa, qb) = to2<T>(Va);
+    if (da) {
+      // for the point (ma, qb): X(n1 - ma, .) = X(qa, .), never at index n
+      const T y_ab = X[1], y_mr = X[0];
+      const T y_mc = qb == 0 ? T(0) : X[3];
+      const T y_mm = qb == 0 ? T(0) : X[2];
+      const cx<T> Vm = conj(W1[1] * W2[1]) * cx<T>{y_ab - y_mm, -(y_mr + y_mc)};
+      *spectrum_at<T>(a, f, ma, qb) = to2<T>(Vm);
+    }
+  }
+}
+
+template <typename T, int NMAX>
+hipError_t launch_quad(const K9Args& a, hipStream_t s) {
+  const int total = (a.ny / 2 + 1) * (a.nx / 2 + 1);
+  hipLaunchKernelGGL((dst_quad<T, NMAX>), dim3((total + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad_f32(const K9Args& a, hipStream_t s) {
+  if (a.N <= 8) return launch_quad<float, 8>(a, s);
+  if (a.N <= 16) return launch_quad<float, 16>(a, s);
+  if (a.N <= 24) return launch_quad<float, 24>(a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_quad_f64(const K9Args& a, hipStream_t s) {
+  if (a.N <= 8) return launch_quad<double, 8>(a, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_dst_pre(const void* members, const void* data, int N, int ny, int nx, void* v, int dtype,
+                          hipStream_t s) {
+  const size_t total = (size_t)(N + 1) * ny * nx;
+  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(dst_pre<float>, grid, block, 0, s, static_cast<const float*>(members),
+                       static_cast<const float*>(data), N, ny, nx, static_cast<float*>(v));
+  else
+    hipLaunchKernelGGL(dst_pre<double>, grid, block, 0, s, static_cast<const double*>(members),
+                       static_cast<const double*>(data), N, ny, nx, static_cast<double*>(v));
+  return hipGetLastError();
+}
+
+hipError_t launch_dst_post(const void* v, int N, int ny, int nx, void* out, int dtype, hipStream_t s) {
+  const size_t total = (size_t)N * ny * nx;
+  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(dst_post<float>, grid, block, 0, s, static_cast<const float*>(v), N, ny, nx,
+                       static_cast<float*>(out));
+  else
+    hipLaunchKernelGGL(dst_post<double>, grid, block, 0, s, static_cast<const double*>(v), N, ny, nx,
+                       static_cast<double*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_dst_quad(const K9Args& a, int dtype, hipStream_t s) {
+  return dtype == 0 ? launch_quad_f32(a, s) : launch_quad_f64(a, s);
+}
+
+}  // namespace fftenkf

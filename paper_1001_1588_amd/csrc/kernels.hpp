@@ -160,6 +160,22 @@ struct K8Args {
 hipError_t launch_k8_gather(const K8Args& a, int dtype, hipStream_t s);
 hipError_t launch_k8_scatter(const K8Args& a, int dtype, hipStream_t s);
 
+// The analysis in the sine basis (k9_dst.hip): the per-bin kernel reads and
+// writes the transformed fields in the workspace layout of K2Args.
+struct K9Args {
+  void* ws_main;
+  void* ws_nyq;
+  const void* R_dst;  // [ny][nx] eigenvalues of R in the sine basis, or nullptr
+  double r_scalar;
+  int N, ny, nx, R, L;
+  uint32_t key0, key1;
+  void* dbg_coeffs;  // test export: [N+1][ny][nx] orthonormal sine coefficients, or nullptr
+};
+hipError_t launch_dst_pre(const void* members, const void* data, int N, int ny, int nx, void* v, int dtype,
+                          hipStream_t s);
+hipError_t launch_dst_post(const void* v, int N, int ny, int nx, void* out, int dtype, hipStream_t s);
+hipError_t launch_dst_quad(const K9Args& a, int dtype, hipStream_t s);
+
 // Device address of the W_4096^k table (float2 for dtype 0, double2 for 1) on
 // the current device, filled from float64 host values on first use.
 hipError_t twiddle_table(int dtype, const void** out);

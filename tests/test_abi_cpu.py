@@ -204,3 +204,17 @@ def test_batch_validation_and_tuning(built_lib):
     assert lib.fftenkf_set_tile_rows(256, 256, 0, 8) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 8
     assert lib.fftenkf_set_tile_rows(256, 256, 0, 0) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 16
     assert lib.fftenkf_set_tile_rows(256, 256, 0, 4) == _lib.EUNSUPPORTED
+
+
+def test_dst_validation(built_lib):
+    lib = _lib.lib()
+    e = _ens(workspace_bytes=1 << 30)
+    assert lib.fftenkf_analyze_dst(ctypes.byref(e), None, None, 1, 0x300000) == _lib.EINVAL
+    assert lib.fftenkf_analyze_dst(ctypes.byref(_ens(workspace_bytes=1000)), 0x200000, None, 1, 0x300000) == _lib.EINVAL
+    assert lib.fftenkf_analyze_dst(ctypes.byref(_ens(ny=12)), 0x200000, None, 1, 0x300000) == _lib.EUNSUPPORTED
+    e2 = _ens(workspace_bytes=1 << 30, r_scalar=-1.0)
+    assert lib.fftenkf_analyze_dst(ctypes.byref(e2), 0x200000, None, 1, 0x300000) == _lib.EINVAL
+    # the sine-basis workspace adds (N+1) real planes to the spectral one
+    for (N, ny, nx, dt, s) in [(20, 2048, 2048, 0, 4), (5, 64, 64, 1, 8)]:
+        base = lib.fftenkf_workspace_bytes(N, ny, nx, dt)
+        assert lib.fftenkf_workspace_bytes_dst(N, ny, nx, dt) == (base + (N + 1) * ny * nx * s + 255) // 256 * 256

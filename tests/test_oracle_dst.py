@@ -88,3 +88,13 @@ def test_noise_convention_statistics():
     # a different stream from the periodic analysis' perturbations
     per = enkf.spectral_noise(123, 2, 64, 64)
     assert not np.allclose(z[0, :8, :8], per[0, :8, :8].real * np.sqrt(2))
+
+
+def test_fft_method_equals_matrices():
+    x = np.random.default_rng(7).standard_normal((2, 16, 32))
+    assert np.allclose(dst.dst2(x, "fft"), dst.dst2(x), atol=1e-12)
+    assert np.allclose(dst.idst2(x, "fft"), dst.idst2(x), atol=1e-12)
+    tw = twin.random_ensemble(16, 32, 4, seed=3, dtype=np.float64)
+    a = dst.analyze_dst(tw.ens, tw.data, 0.02, 5, method="fft")
+    b = dst.analyze_dst(tw.ens, tw.data, 0.02, 5)
+    assert np.allclose(a, b, atol=1e-12)
