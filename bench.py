@@ -13,7 +13,8 @@ second leg times the learned spectral covariance at 2048 x 2048, N = 5 (and the
 plain analysis at the same size), with the perceptron's matrix-core rate and the
 analysis RMSE of the plain, learned and exact-covariance filters; a third times
 the multi-block analysis (4 fields of 1024 x 1024, N = 10); a fourth runs 256
-independent filters of uneven size, autotuned and captured in one graph.
+independent filters of uneven size, autotuned and captured in one graph; a
+fifth times the analysis in the real sine basis on the main workload.
 """
 
 from __future__ import annotations
@@ -312,6 +313,34 @@ def batch_leg(args, dev) -> dict:
     }
 
 
+def dst_leg(args, dev) -> dict:
+    """The analysis in the real sine basis on the main workload's ensemble
+    (2048 x 2048, N = 20, float32, R = 0.05 I): time per analysis."""
+    import torch
+
+    from paper_1001_1588_amd import _lib, twin
+
+    tw = twin.workload("large2048", seed=args.seed)
+    N, ny, nx = tw.ens.shape
+    ens = torch.from_numpy(tw.ens).to(dev)
+    data = torch.from_numpy(tw.data).to(dev)
+    ws = torch.empty(int(_lib.lib().fftenkf_workspace_bytes_dst(N, ny, nx, 0)), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(ens)
+    for s in range(args.warmup):
+        _lib.analyze_dst(ens, data, 0.05, tw.seed + s, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for s in range(args.dst_steps):
+        _lib.analyze_dst(ens, data, 0.05, tw.seed + s, out=out, workspace=ws)
+    z.record()
+    z.synchronize()
+    ms = a.elapsed_time(z) / args.dst_steps
+    return {"workload": "2048x2048 grid, N=20 members, float32, spectrum |k|^-3, R=0.05 I, orthonormal DST-II basis",
+            "unit": "member-gridpoints/s", "value": N * ny * nx / (ms * 1e-3), "ms_per_step": ms,
+            "steps": args.dst_steps}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,6 +351,7 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the device copy ceiling probe (0 = skip)")
     ap.add_argument("--batch-filters", type=int, default=256, help="filters of the batched leg (0 = skip)")
+    ap.add_argument("--dst-steps", type=int, default=20, help="timed analyses of the sine-basis leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--multi-steps", type=int, default=20,
                     help="timed analyses of the multi-block leg (0 = skip)")
@@ -423,6 +453,8 @@ def main() -> int:
         result["multiblock"] = multiblock_leg(args, hip, dev)
     if args.batch_filters > 0:
         result["batch"] = batch_leg(args, dev)
+    if args.dst_steps > 0:
+        result["sine_basis"] = dst_leg(args, dev)
     if args.cpu_members > 0:
         result["cpu_baseline"] = cpu_baseline(tw, min(args.cpu_members, N))
     print(json.dumps(result), flush=True)

@@ -34,6 +34,7 @@ SOURCES = {
     "k6_multiblock": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "k2_spectral.hpp",
                                CSRC + "k6_multiblock.hpp"],
     "k7_spectral_mlp": [CSRC + "kernels.hpp", CSRC + "k7_spectral_mlp.hip"],
+    "dst_": [CSRC + "fft_core.hpp", CSRC + "kernels.hpp", CSRC + "philox.hpp", CSRC + "k9_dst.hip"],
 }
 COPY = "__amd_rocclr_copyBuffer"
 
@@ -53,7 +54,7 @@ def sources_hash(files) -> str:
 
 
 def short(name: str) -> str:
-    return name.split("(")[0].replace("void ", "").strip()
+    return name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").strip()
 
 
 def read_csv(pattern: str):
@@ -66,9 +67,12 @@ def read_csv(pattern: str):
 def summarise(base: str, copy_mib: int) -> dict:
     durs = collections.defaultdict(list)
     for r in read_csv(os.path.join(base, "trace", "*kernel_trace.csv")):
-        key = (short(r["Kernel_Name"]), int(r["Grid_Size"]) if "Grid_Size" in r else int(r["Grid_Size_X"]))
-        durs[key].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        # total threads, as the counter records give it
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) if "Grid_Size_X" in r \
+            else int(r["Grid_Size"])
+        durs[(short(r["Kernel_Name"]), grid)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     counters = {}
+    copy_max = {}
     for kind, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
         vals = collections.defaultdict(list)
         for r in read_csv(os.path.join(base, kind, "*counter_collection.csv")):
@@ -76,13 +80,11 @@ def summarise(base: str, copy_mib: int) -> dict:
                 continue
             vals[(short(r["Kernel_Name"]), int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
         counters[kind] = {k: sum(v) / len(v) for k, v in vals.items()}
-    copy_bytes = 2 * (copy_mib << 20)
-    scale = {}
-    for kind in ("fetch", "write"):
         # the largest copy dispatch is bench.py's reference copy: it reads copy_mib
-        # MiB and writes copy_mib MiB
-        cp = [v for (n, _), v in counters[kind].items() if n == COPY]
-        scale[kind] = (copy_bytes / 2) / max(cp) if cp else None
+        # MiB and writes copy_mib MiB (other copies of the same kernel are small)
+        copy_max[kind] = max((max(v) for (n, _), v in vals.items() if n == COPY), default=None)
+    copy_bytes = 2 * (copy_mib << 20)
+    scale = {kind: ((copy_bytes / 2) / copy_max[kind] if copy_max[kind] else None) for kind in ("fetch", "write")}
     kernels = []
     for (name, grid), d in sorted(durs.items(), key=lambda kv: -sum(kv[1])):
         fam = family(name)
