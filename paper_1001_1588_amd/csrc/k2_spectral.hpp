@@ -11,7 +11,8 @@
 // thread-local.  The inverse transform starts from exactly those bins and ends
 // on the y1 positions the thread loaded, which it overwrites in place.  The
 // exchanges between passes go through two LDS buffers in turn (one block
-// synchronisation each); every field's loads are issued before any transform.
+// synchronisation each); every field's loads are issued before any transform,
+// and each inverse round first draws and applies its members' update.
 //
 // The unit geometry (main and Nyquist units, XCD grouping) is spectral_unit.hpp.
 #pragma once
@@ -43,6 +44,61 @@ struct K2Geom {
   static constexpr size_t lds_bytes() { return 2 * (size_t)FB * seqp<L>() * sizeof(V2<T>); }
 };
 
+// The perturbation of one bin: Philox counter word 0 (the bin's canonical
+// index gy * (nx/2 + 1) + kx) and the scales of the real and imaginary parts.
+// In the kx = 0 and kx = nx/2 columns the bins above ny/2 take the conjugate of
+// their mirror's draw and the self-conjugate bins a real draw of full variance.
+template <typename T>
+struct BinNoise {
+  uint32_t ctr0;
+  T zs, zi;
+};
+
+template <typename T>
+__device__ __forceinline__ BinNoise<T> bin_noise(int kx, int ky, int nxh, int ny) {
+  const bool edge = (kx == 0) || (kx == nxh);
+  const bool mirrored = edge && ky > (ny >> 1);
+  const bool selfconj = edge && (ky == 0 || ky == (ny >> 1));
+  const int gy = mirrored ? ny - ky : ky;
+  BinNoise<T> b;
+  b.ctr0 = (uint32_t)(gy * (nxh + 1) + kx);
+  b.zs = selfconj ? T(1) : T(0.70710678118654752440);
+  b.zi = selfconj ? T(0) : (mirrored ? -b.zs : b.zs);
+  return b;
+}
+
+// e_hat of members 2p and 2p + 1 at one bin, amp = sqrt(n R) (the unnormalised
+// spectrum's scale): one Philox call, counter (ctr0, p, 0, 0), two Box-Muller pairs.
+template <typename T>
+__device__ __forceinline__ void draw_pair(const BinNoise<T>& b, int p, uint32_t key0, uint32_t key1, T amp,
+                                          cx<T>& e0, cx<T>& e1) {
+  const u32x4 w = philox4x32_10(u32x4{b.ctr0, (uint32_t)p, 0u, 0u}, key0, key1);
+  T za, zb;
+  box_muller<T>(w.x0, w.x1, za, zb);
+  e0 = cx<T>{amp * b.zs * za, amp * b.zi * zb};
+  box_muller<T>(w.x2, w.x3, za, zb);
+  e1 = cx<T>{amp * b.zs * za, amp * b.zi * zb};
+}
+
+// Eq. (2) at point i of a thread: the sample variance of the N members'
+// unnormalised coefficients times var_scale = 1 / ((N - 1) n).
+template <typename T, int NMAX, int P>
+__device__ __forceinline__ T sample_variance(const cx<T> (&u)[NMAX][P], int i, int N, T invN, T var_scale) {
+  cx<T> mean{T(0), T(0)};
+#pragma unroll
+  for (int f = 0; f < NMAX; ++f)
+    if (f < N) mean = mean + u[f][i];
+  mean = scale(mean, invN);
+  T var = T(0);
+#pragma unroll
+  for (int f = 0; f < NMAX; ++f)
+    if (f < N) {
+      const cx<T> d = u[f][i] - mean;
+      var += d.re * d.re + d.im * d.im;
+    }
+  return var * var_scale;
+}
+
 // SPLIT compiles the modes that start or stop at the transformed fields
 // (K2_STATS, K2_UPDATE_LEARNED, K2_INVERSE); the single-pass modes are compiled
 // without them.
@@ -53,7 +109,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   constexpr int TF2 = L / P;
   constexpr int FB = K2Geom<T>::FB;
   constexpr int SEQP = K2Geom<T>::template seqp<L>();
-  static_assert(NMAX % FB == 0 && NMAX % 2 == 0, "member bucket must be a multiple of the LDS batch");
+  static_assert(NMAX % FB == 0 && FB % 2 == 0, "member bucket must be a multiple of the LDS batch");
   extern __shared__ unsigned char k2_lds_raw[];  // two buffers of FB fields
 
   const V2<T>* __restrict__ tab = static_cast<const V2<T>*>(a.tab);
@@ -131,19 +187,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     ky[i] = k2 + R * (t2 + TF2 * i);
-    cx<T> mean{T(0), T(0)};
-#pragma unroll
-    for (int f = 0; f < NMAX; ++f)
-      if (f < N) mean = mean + u[f][i];
-    mean = scale(mean, invN);
-    T var = T(0);
-#pragma unroll
-    for (int f = 0; f < NMAX; ++f)
-      if (f < N) {
-        const cx<T> d = u[f][i] - mean;
-        var += d.re * d.re + d.im * d.im;
-      }
-    T chat = var * var_scale;
+    T chat = sample_variance<T, NMAX, P>(u, i, N, invN, var_scale);
     if (a.lam_map != nullptr && valid_w) chat = static_cast<const T*>(a.lam_map)[(size_t)ky[i] * nh + kx];
     T rb = T(a.r_scalar);
     if (Rspec != nullptr && valid_w) rb = Rspec[(size_t)ky[i] * nh + kx];
@@ -196,47 +240,47 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
     return;
   }
 
-  // ---- perturbations and update, two members per Philox call
-  const bool edge = (kx == 0) || (kx == nxh);
-  if (!(SPLIT && a.mode == K2_INVERSE)) static_for<0, P>([&](auto I) __attribute__((always_inline)) {
-    constexpr int i = decltype(I)::value;
-    const bool mirrored = edge && ky[i] > (ny >> 1);
-    const bool selfconj = edge && (ky[i] == 0 || ky[i] == (ny >> 1));
-    const int gy = mirrored ? ny - ky[i] : ky[i];
-    const uint32_t ctr0 = (uint32_t)(gy * nh + kx);
-    const T zs = selfconj ? T(1) : T(0.70710678118654752440);
-    const T zi = selfconj ? T(0) : (mirrored ? -zs : zs);
-    static_for<0, NMAX / 2>([&](auto PP) __attribute__((always_inline)) {
-      constexpr int p = decltype(PP)::value;
-      if (2 * p < N) {
-        const u32x4 w = philox4x32_10(u32x4{ctr0, (uint32_t)p, 0u, 0u}, a.key0, a.key1);
-        T za, zb;
-        box_muller<T>(w.x0, w.x1, za, zb);
-        const cx<T> e0{amp[i] * zs * za, amp[i] * zi * zb};
-        box_muller<T>(w.x2, w.x3, za, zb);
-        const cx<T> e1{amp[i] * zs * za, amp[i] * zi * zb};
-        if (a.mode == K2_DEBUG_PERTURB) {
-          if (valid_w) {
-            V2<T>* ep = static_cast<V2<T>*>(a.dbg_e);
-            const T us = T(1) / sqrt_t<T>(n_tot);
-            const size_t bin = (size_t)ky[i] * nh + kx, plane = (size_t)ny * nh;
-            ep[(2 * p) * plane + bin] = to2<T>(scale(e0, us));
-            if (2 * p + 1 < N) ep[(2 * p + 1) * plane + bin] = to2<T>(scale(e1, us));
+  // ---- perturbations and update, two members per Philox call: the pairs
+  // [PB, PE) of every bin the thread holds
+  auto perturb = [&](auto PB, auto PE) __attribute__((always_inline)) {
+    static_for<0, P>([&](auto I) __attribute__((always_inline)) {
+      constexpr int i = decltype(I)::value;
+      const BinNoise<T> bn = bin_noise<T>(kx, ky[i], nxh, ny);
+      static_for<decltype(PB)::value, decltype(PE)::value>([&](auto PP) __attribute__((always_inline)) {
+        constexpr int p = decltype(PP)::value;
+        if (2 * p < N) {
+          cx<T> e0, e1;
+          draw_pair<T>(bn, p, a.key0, a.key1, amp[i], e0, e1);
+          if (a.mode == K2_DEBUG_PERTURB) {  // test export of e_hat (unitary scale)
+            if (valid_w) {
+              V2<T>* ep = static_cast<V2<T>*>(a.dbg_e);
+              const T us = T(1) / sqrt_t<T>(n_tot);
+              const size_t bin = (size_t)ky[i] * nh + kx, plane = (size_t)ny * nh;
+              ep[(2 * p) * plane + bin] = to2<T>(scale(e0, us));
+              if (2 * p + 1 < N) ep[(2 * p + 1) * plane + bin] = to2<T>(scale(e1, us));
+            }
+          } else {
+            const cx<T> ua = u[2 * p][i], ub = u[2 * p + 1][i];
+            u[2 * p][i] = ua + scale(dv[0][i] + e0 - ua, gain[i]);
+            if (2 * p + 1 < N) u[2 * p + 1][i] = ub + scale(dv[0][i] + e1 - ub, gain[i]);
           }
-        } else {
-          const cx<T> ua = u[2 * p][i], ub = u[2 * p + 1][i];
-          u[2 * p][i] = ua + scale(dv[0][i] + e0 - ua, gain[i]);
-          if (2 * p + 1 < N) u[2 * p + 1][i] = ub + scale(dv[0][i] + e1 - ub, gain[i]);
         }
-      }
+      });
     });
-  });
-  if (a.mode == K2_DEBUG_PERTURB) return;  // no synchronisation follows
+  };
+  if (a.mode == K2_DEBUG_PERTURB) {
+    perturb(std::integral_constant<int, 0>{}, std::integral_constant<int, NMAX / 2>{});
+    return;  // no synchronisation follows
+  }
 
-  // ---- inverse length-L transforms, written back in place
-#pragma unroll
-  for (int f0 = 0; f0 < NMAX; f0 += FB) {
+  // ---- per LDS round: update its members (their perturbations are drawn here,
+  // so the stores of one round overlap the arithmetic of the next), then the
+  // inverse length-L transforms, written back in place
+  static_for<0, NMAX, FB>([&](auto F0) __attribute__((always_inline)) {
+    constexpr int f0 = decltype(F0)::value;
     if (f0 < N) {
+      if (!(SPLIT && a.mode == K2_INVERSE))
+        perturb(std::integral_constant<int, f0 / 2>{}, std::integral_constant<int, (f0 + FB) / 2>{});
       cx<T> blk[FB][P];
 #pragma unroll
       for (int b = 0; b < FB; ++b)
@@ -253,7 +297,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
           }
       }
     }
-  }
+  });
 }
 
 template <typename T, int L, int NMAX, bool SPLIT>
