@@ -222,7 +222,8 @@ int fftenkf_tile_rows(int ny, int nx, int dtype);
  */
 int fftenkf_analyze_dst(const fftenkf_ens* ens, const void* data, const void* R_dst, uint64_t seed, void* out);
 
-/* Workspace bytes of fftenkf_analyze_dst and fftenkf_debug_dst_coeffs; 0 if invalid. */
+/* Workspace bytes of fftenkf_analyze_dst and fftenkf_debug_dst_coeffs (the
+ * same as fftenkf_workspace_bytes); 0 if invalid. */
 size_t fftenkf_workspace_bytes_dst(int n_members, int ny, int nx, int dtype);
 
 /* Test-only: the orthonormal sine coefficients [N+1][ny][nx] (members, then

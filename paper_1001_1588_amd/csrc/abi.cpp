@@ -613,13 +613,12 @@ int run_batch(int N, int dtype, const fftenkf_filter* fs, int n, const std::vect
 
 // Workspace of the sine-basis analysis: the spectral workspace, then the
 // reordered fields v of Makhoul's form ((N+1) planes of ny * nx reals).
-size_t dst_ws_bytes(const Plan& plan, int N, int ny, int nx, int dtype) {
-  return round256(plan.ws_bytes + (size_t)(N + 1) * ny * nx * dsize(dtype));
-}
+// The sine-basis analysis uses the periodic analysis' workspace.
+size_t dst_ws_bytes(const Plan& plan, int, int, int, int) { return plan.ws_bytes; }
 
-// pre (x -> v), sweep 1, the statistics mode of sweep 2, the per-bin sine-basis
-// kernel, then (for an analysis) the inverse-only mode of sweep 2, sweep 3 and
-// post (v -> x).
+// Sweep 1 through the sine reordering, the statistics mode of sweep 2, the
+// per-bin sine-basis kernel, then (for an analysis) the inverse-only mode of
+// sweep 2 and sweep 3 back through the reordering.
 int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_dst, uint64_t seed, void* out,
             void* dbg_coeffs) {
   if (t_fail_next != 0) {
@@ -634,12 +633,9 @@ int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void
   char* ws = static_cast<char*>(e->workspace);
   void* ws_main = ws;
   void* ws_nyq = ws + plan.off_nyq;
-  char* v = ws + plan.ws_bytes;
   const int N = e->n_members, ny = e->ny, nx = e->nx;
-  const size_t field = (size_t)ny * nx * dsize(e->dtype);
-  err = launch_dst_pre(e->members, data, N, ny, nx, v, e->dtype, stream);
-  K1Args a1{v, v + (size_t)N * field, N, ny, nx, plan.R, plan.L, ws_main, ws_nyq, tab};
-  if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
+  K1Args a1{e->members, data, N, ny, nx, plan.R, plan.L, ws_main, ws_nyq, tab, 1};
+  err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
   K2Args a2{};
   a2.ws_main = ws_main;
   a2.ws_nyq = ws_nyq;
@@ -665,9 +661,8 @@ int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void
   if (err == hipSuccess && dbg_coeffs == nullptr) {
     a2.mode = K2_INVERSE;
     err = k2();
-    K3Args a3{ws_main, ws_nyq, N, ny, nx, plan.R, plan.L, v, tab};
+    K3Args a3{ws_main, ws_nyq, N, ny, nx, plan.R, plan.L, out, tab, 1};
     if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
-    if (err == hipSuccess) err = launch_dst_post(v, N, ny, nx, out, e->dtype, stream);
   }
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sine-basis analysis launch: %s", hipGetErrorString(err));
   return FFTENKF_OK;

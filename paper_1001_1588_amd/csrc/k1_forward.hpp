@@ -25,7 +25,10 @@ struct K1Geom {
 };
 
 // The work of one block; `block` is its index within one analysis.
-template <typename T, int NX, int R, int SB>
+// SINE: the fields enter through the sine-basis reordering v(j1, j2) =
+// (-1)^(i1 + i2) x(i1, i2), i = dst_rho(j): row j1 reads row i1, and the
+// thread's x position j2 reads x(2 j2) for j2 < NX/2, -x(2 (NX - 1 - j2) + 1) above.
+template <typename T, int NX, int R, int SB, bool SINE>
 __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* __restrict__ data, int N, int ny,
                                         int L, V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq,
                                         const V2<T>* __restrict__ tab, unsigned block) {
@@ -51,9 +54,25 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
   T a[R][P];
 #pragma unroll
   for (int y2 = 0; y2 < R; ++y2) {
-    const T* __restrict__ row = src + (size_t)(y1 + L * y2) * NX + t;
+    if constexpr (SINE) {
+      // j1 = y1 + L y2 < ny/2 exactly when y2 < R/2 (R is even): row 2 j1, else
+      // 2 (ny - 1 - j1) + 1; likewise j2 = t + TF i < NX/2 exactly when i < P/2.
+      // The signs are therefore constants.
+      const uint32_t step = 2u * (uint32_t)L * NX * (uint32_t)sizeof(T);
+      const uint32_t rowoff = y2 < R / 2 ? (2u * (uint32_t)y1 * NX) * (uint32_t)sizeof(T) + (uint32_t)y2 * step
+                                         : ((2u * (uint32_t)(ny - y1) - 1u) * NX) * (uint32_t)sizeof(T) - (uint32_t)y2 * step;
 #pragma unroll
-    for (int i = 0; i < P; ++i) a[y2][i] = active ? row[TF * i] : T(0);
+      for (int i = 0; i < P; ++i) {
+        const int j2 = t + TF * i;
+        const uint32_t i2 = (uint32_t)(i < P / 2 ? 2 * j2 : 2 * (NX - 1 - j2) + 1);
+        const T x = active ? ld_off(src, rowoff + i2 * (uint32_t)sizeof(T)) : T(0);
+        a[y2][i] = ((y2 >= R / 2) != (i >= P / 2)) ? -x : x;
+      }
+    } else {
+      const T* __restrict__ row = src + (size_t)(y1 + L * y2) * NX + t;
+#pragma unroll
+      for (int i = 0; i < P; ++i) a[y2][i] = active ? row[TF * i] : T(0);
+    }
   }
 
   // 2. real R-point DFT over y2, packed into R/2 complex sequences
@@ -141,18 +160,18 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
   }
 }
 
-template <typename T, int NX, int R, int SB>
+template <typename T, int NX, int R, int SB, bool SINE>
 __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
     const T* __restrict__ members, const T* __restrict__ data, int N, int ny, int L,
     V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq, const V2<T>* __restrict__ tab) {
-  k1_body<T, NX, R, SB>(members, data, N, ny, L, ws_main, ws_nyq, tab, blockIdx.x);
+  k1_body<T, NX, R, SB, SINE>(members, data, N, ny, L, ws_main, ws_nyq, tab, blockIdx.x);
 }
 
 // A batch of analyses on one grid: blockIdx.y selects the analysis.
 template <typename T, int NX, int R, int SB>
 __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward_batch(const BatchArgs b) {
   const BatchFilter& f = b.f[blockIdx.y];
-  k1_body<T, NX, R, SB>(static_cast<const T*>(f.members), static_cast<const T*>(f.data), b.N, b.ny, b.L,
+  k1_body<T, NX, R, SB, false>(static_cast<const T*>(f.members), static_cast<const T*>(f.data), b.N, b.ny, b.L,
                         static_cast<V2<T>*>(f.ws_main), static_cast<V2<T>*>(f.ws_nyq),
                         static_cast<const V2<T>*>(b.tab), blockIdx.x);
 }
@@ -180,9 +199,14 @@ hipError_t launch_k1_shape(const K1Args& a, hipStream_t st) {
   constexpr int SB = k1_sb<T, NX, R>();
   const int tiles = (a.N + 1) * a.L;
   const dim3 grid((tiles + Geo::G - 1) / Geo::G), block(Geo::threads);
-  hipLaunchKernelGGL((k1_forward<T, NX, R, SB>), grid, block, 0, st, static_cast<const T*>(a.members),
-                     static_cast<const T*>(a.data), a.N, a.ny, a.L, static_cast<V2<T>*>(a.ws_main),
-                     static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab));
+  if (a.sine)
+    hipLaunchKernelGGL((k1_forward<T, NX, R, SB, true>), grid, block, 0, st, static_cast<const T*>(a.members),
+                       static_cast<const T*>(a.data), a.N, a.ny, a.L, static_cast<V2<T>*>(a.ws_main),
+                       static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab));
+  else
+    hipLaunchKernelGGL((k1_forward<T, NX, R, SB, false>), grid, block, 0, st, static_cast<const T*>(a.members),
+                       static_cast<const T*>(a.data), a.N, a.ny, a.L, static_cast<V2<T>*>(a.ws_main),
+                       static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab));
   return hipGetLastError();
 }
 

@@ -22,7 +22,9 @@
 namespace fftenkf {
 
 // The work of one block; `block` is its index within one analysis.
-template <typename T, int NX, int R, int SB>
+// SINE: row j1, x position j2 of the result goes to out(i1, i2) times
+// (-1)^(i1 + i2), i = dst_rho(j) (the converse of sweep 1's reordering).
+template <typename T, int NX, int R, int SB, bool SINE>
 __device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ ws_nyq, int N,
                                         int ny, int L, T out_scale, T* __restrict__ out,
                                         const V2<T>* __restrict__ tab, int block) {
@@ -124,24 +126,40 @@ __device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, const
       for (int j = 1; j < H; ++j) V[j] = s[j][i];
       T col[R];
       irdft<T, R>(V, col);
+      if constexpr (SINE) {
+        // row j1 = y1 + L y2 goes to 2 j1 for y2 < R/2 and to 2 (ny - 1 - j1) + 1
+        // above (R is even); column j2 = t + TF i likewise with i < P/2
+        const int j2 = t + TF * i;
+        const uint32_t i2 = (uint32_t)(i < P / 2 ? 2 * j2 : 2 * (NX - 1 - j2) + 1);
+        const uint32_t step = 2u * (uint32_t)L * NX * (uint32_t)sizeof(T);
+        const uint32_t even = (2u * (uint32_t)y1 * NX + i2) * (uint32_t)sizeof(T);
+        const uint32_t odd = ((2u * (uint32_t)(ny - y1) - 1u) * NX + i2) * (uint32_t)sizeof(T);
+        T* __restrict__ fo = out + (size_t)f * ny * NX;
 #pragma unroll
-      for (int y2 = 0; y2 < R; ++y2) dst[(size_t)(y1 + L * y2) * NX + TF * i] = col[y2];
+        for (int y2 = 0; y2 < R; ++y2) {
+          const T v = ((y2 >= R / 2) != (i >= P / 2)) ? -col[y2] : col[y2];
+          st_off(fo, y2 < R / 2 ? even + (uint32_t)y2 * step : odd - (uint32_t)y2 * step, v);
+        }
+      } else {
+#pragma unroll
+        for (int y2 = 0; y2 < R; ++y2) dst[(size_t)(y1 + L * y2) * NX + TF * i] = col[y2];
+      }
     }
   }
 }
 
-template <typename T, int NX, int R, int SB>
-__global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse(
+template <typename T, int NX, int R, int SB, bool SINE>
+__global__ __launch_bounds__((K1Geom<T, NX>::threads), (SINE ? 2 : 1)) void k3_inverse(
     const V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ ws_nyq, int N, int ny, int L, T out_scale,
     T* __restrict__ out, const V2<T>* __restrict__ tab) {
-  k3_body<T, NX, R, SB>(ws_main, ws_nyq, N, ny, L, out_scale, out, tab, blockIdx.x);
+  k3_body<T, NX, R, SB, SINE>(ws_main, ws_nyq, N, ny, L, out_scale, out, tab, blockIdx.x);
 }
 
 // A batch of analyses on one grid: blockIdx.y selects the analysis.
 template <typename T, int NX, int R, int SB>
 __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse_batch(const BatchArgs b) {
   const BatchFilter& f = b.f[blockIdx.y];
-  k3_body<T, NX, R, SB>(static_cast<const V2<T>*>(f.ws_main), static_cast<const V2<T>*>(f.ws_nyq), b.N, b.ny, b.L,
+  k3_body<T, NX, R, SB, false>(static_cast<const V2<T>*>(f.ws_main), static_cast<const V2<T>*>(f.ws_nyq), b.N, b.ny, b.L,
                         T(1) / (T(b.nx) * T(b.ny)), static_cast<T*>(f.out), static_cast<const V2<T>*>(b.tab),
                         blockIdx.x);
 }
@@ -162,9 +180,14 @@ hipError_t launch_k3_shape(const K3Args& a, hipStream_t st) {
   const int tiles = a.N * a.L;
   const dim3 grid((tiles + Geo::G - 1) / Geo::G), block(Geo::threads);
   const T out_scale = T(1) / (T(a.nx) * T(a.ny));
-  hipLaunchKernelGGL((k3_inverse<T, NX, R, SB>), grid, block, 0, st, static_cast<const V2<T>*>(a.ws_main),
-                     static_cast<const V2<T>*>(a.ws_nyq), a.N, a.ny, a.L, out_scale, static_cast<T*>(a.out),
-                     static_cast<const V2<T>*>(a.tab));
+  if (a.sine)
+    hipLaunchKernelGGL((k3_inverse<T, NX, R, SB, true>), grid, block, 0, st, static_cast<const V2<T>*>(a.ws_main),
+                       static_cast<const V2<T>*>(a.ws_nyq), a.N, a.ny, a.L, out_scale, static_cast<T*>(a.out),
+                       static_cast<const V2<T>*>(a.tab));
+  else
+    hipLaunchKernelGGL((k3_inverse<T, NX, R, SB, false>), grid, block, 0, st, static_cast<const V2<T>*>(a.ws_main),
+                       static_cast<const V2<T>*>(a.ws_nyq), a.N, a.ny, a.L, out_scale, static_cast<T*>(a.out),
+                       static_cast<const V2<T>*>(a.tab));
   return hipGetLastError();
 }
 

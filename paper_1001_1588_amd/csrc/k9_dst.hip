@@ -11,10 +11,11 @@
 // with X = 0 at index n.  The orthonormal coefficient is alpha1(k1) alpha2(k2)
 // X(k1, k2), alpha(0) = sqrt(1/n), alpha(k > 0) = sqrt(2/n).
 //
-// Launches: dst_pre (x -> v for the members and d), sweep 1 and the statistics
-// mode of sweep 2 (V left in the workspace), dst_quad (per mirror set of bins:
-// V -> X -> eq. (2)-(3) in the sine basis -> X^a -> V^a), the inverse-only mode
-// of sweep 2 and sweep 3 (V^a -> v^a), dst_post (v^a -> x^a).
+// Launches: sweep 1 reading x through the reordering (x -> V, members and d)
+// and the statistics mode of sweep 2 (V left in the workspace), dst_quad (per
+// mirror set of bins: V -> X -> eq. (2)-(3) in the sine basis -> X^a -> V^a),
+// the inverse-only mode of sweep 2 and sweep 3 writing through the reordering
+// (V^a -> x^a).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -26,8 +27,6 @@ namespace fftenkf {
 
 namespace {
 
-__device__ __forceinline__ int rho(int j, int n) { return j < n / 2 ? 2 * j : 2 * (n - 1 - j) + 1; }
-__device__ __forceinline__ int rho_inv(int i, int n) { return (i & 1) ? n - 1 - (i >> 1) : (i >> 1); }
 
 template <typename T> __device__ __forceinline__ void sincospi_t(T x, T* s, T* c);
 template <> __device__ __forceinline__ void sincospi_t<float>(float x, float* s, float* c) { sincospif(x, s, c); }
@@ -44,36 +43,6 @@ __device__ __forceinline__ cx<T> wq(int k, int n) {
 template <typename T> __device__ __forceinline__ T tiny_t();
 template <> __device__ __forceinline__ float tiny_t<float>() { return 1.17549435e-38f; }
 template <> __device__ __forceinline__ double tiny_t<double>() { return 2.2250738585072014e-308; }
-
-// v(j1, j2) = (-1)^(i1 + i2) x(i1, i2), (i1, i2) = (rho(j1), rho(j2)), for the
-// N members and d (field N); one thread per output element.
-template <typename T>
-__global__ void dst_pre(const T* __restrict__ members, const T* __restrict__ data, int N, int ny, int nx,
-                        T* __restrict__ v) {
-  const size_t n = (size_t)ny * nx;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)(N + 1) * n) return;
-  const int f = (int)(idx / n);
-  const size_t e = idx - (size_t)f * n;
-  const int j1 = (int)(e / nx), j2 = (int)(e - (size_t)j1 * nx);
-  const int i1 = rho(j1, ny), i2 = rho(j2, nx);
-  const T* src = f < N ? members + (size_t)f * n : data;
-  const T x = src[(size_t)i1 * nx + i2];
-  v[idx] = ((i1 + i2) & 1) ? -x : x;
-}
-
-// x(i1, i2) = (-1)^(i1 + i2) v(rho^-1(i1), rho^-1(i2)) for the N members.
-template <typename T>
-__global__ void dst_post(const T* __restrict__ v, int N, int ny, int nx, T* __restrict__ out) {
-  const size_t n = (size_t)ny * nx;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)N * n) return;
-  const int f = (int)(idx / n);
-  const size_t e = idx - (size_t)f * n;
-  const int i1 = (int)(e / nx), i2 = (int)(e - (size_t)i1 * nx);
-  const T y = v[(size_t)f * n + (size_t)rho_inv(i1, ny) * nx + rho_inv(i2, nx)];
-  out[idx] = ((i1 + i2) & 1) ? -y : y;
-}
 
 template <typename T>
 __device__ __forceinline__ V2<T>* spectrum_at(const K9Args& a, int f, int ky, int kx) {
@@ -223,31 +192,6 @@ hipError_t launch_quad_f64(const K9Args& a, hipStream_t s) {
 }
 
 }  // namespace
-
-hipError_t launch_dst_pre(const void* members, const void* data, int N, int ny, int nx, void* v, int dtype,
-                          hipStream_t s) {
-  const size_t total = (size_t)(N + 1) * ny * nx;
-  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
-  if (dtype == 0)
-    hipLaunchKernelGGL(dst_pre<float>, grid, block, 0, s, static_cast<const float*>(members),
-                       static_cast<const float*>(data), N, ny, nx, static_cast<float*>(v));
-  else
-    hipLaunchKernelGGL(dst_pre<double>, grid, block, 0, s, static_cast<const double*>(members),
-                       static_cast<const double*>(data), N, ny, nx, static_cast<double*>(v));
-  return hipGetLastError();
-}
-
-hipError_t launch_dst_post(const void* v, int N, int ny, int nx, void* out, int dtype, hipStream_t s) {
-  const size_t total = (size_t)N * ny * nx;
-  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
-  if (dtype == 0)
-    hipLaunchKernelGGL(dst_post<float>, grid, block, 0, s, static_cast<const float*>(v), N, ny, nx,
-                       static_cast<float*>(out));
-  else
-    hipLaunchKernelGGL(dst_post<double>, grid, block, 0, s, static_cast<const double*>(v), N, ny, nx,
-                       static_cast<double*>(out));
-  return hipGetLastError();
-}
 
 hipError_t launch_dst_quad(const K9Args& a, int dtype, hipStream_t s) {
   return dtype == 0 ? launch_quad_f32(a, s) : launch_quad_f64(a, s);

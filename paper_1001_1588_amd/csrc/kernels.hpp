@@ -28,6 +28,7 @@ struct K1Args {
   void* ws_main;
   void* ws_nyq;
   const void* tab;  // W_4096^k table of dtype's complex type (device)
+  int sine;         // 1: transform the sine-basis reordering of the fields (dst_rho)
 };
 
 // K2_STATS: forward transforms and eq. (2) only -- writes c_hat to chat_map,
@@ -105,7 +106,13 @@ struct K3Args {
   int N, ny, nx, R, L;
   void* out;  // [N][ny][nx]
   const void* tab;
+  int sine;  // 1: write the result back through the sine-basis reordering (dst_rho)
 };
+
+// The reordering of the sine-basis analysis (Makhoul): the transformed field is
+// v(j1, j2) = (-1)^(i1 + i2) x(i1, i2) with i = dst_rho(j, n), i.e. the even
+// indices in order, then the odd ones in reverse.
+__host__ __device__ __forceinline__ int dst_rho(int j, int n) { return j < n / 2 ? 2 * j : 2 * (n - 1 - j) + 1; }
 
 // K2 geometry chosen for a given length L (shared by host planning and kernels).
 constexpr int k2_points(int L) { return L < 4 ? L : 4; }
@@ -171,9 +178,6 @@ struct K9Args {
   uint32_t key0, key1;
   void* dbg_coeffs;  // test export: [N+1][ny][nx] orthonormal sine coefficients, or nullptr
 };
-hipError_t launch_dst_pre(const void* members, const void* data, int N, int ny, int nx, void* v, int dtype,
-                          hipStream_t s);
-hipError_t launch_dst_post(const void* v, int N, int ny, int nx, void* out, int dtype, hipStream_t s);
 hipError_t launch_dst_quad(const K9Args& a, int dtype, hipStream_t s);
 
 // Device address of the W_4096^k table (float2 for dtype 0, double2 for 1) on

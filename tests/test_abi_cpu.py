@@ -214,7 +214,6 @@ def test_dst_validation(built_lib):
     assert lib.fftenkf_analyze_dst(ctypes.byref(_ens(ny=12)), 0x200000, None, 1, 0x300000) == _lib.EUNSUPPORTED
     e2 = _ens(workspace_bytes=1 << 30, r_scalar=-1.0)
     assert lib.fftenkf_analyze_dst(ctypes.byref(e2), 0x200000, None, 1, 0x300000) == _lib.EINVAL
-    # the sine-basis workspace adds (N+1) real planes to the spectral one
-    for (N, ny, nx, dt, s) in [(20, 2048, 2048, 0, 4), (5, 64, 64, 1, 8)]:
-        base = lib.fftenkf_workspace_bytes(N, ny, nx, dt)
-        assert lib.fftenkf_workspace_bytes_dst(N, ny, nx, dt) == (base + (N + 1) * ny * nx * s + 255) // 256 * 256
+    # the sine-basis analysis reorders inside sweeps 1 and 3: same workspace
+    for (N, ny, nx, dt) in [(20, 2048, 2048, 0), (5, 64, 64, 1)]:
+        assert lib.fftenkf_workspace_bytes_dst(N, ny, nx, dt) == lib.fftenkf_workspace_bytes(N, ny, nx, dt) > 0
