@@ -17,9 +17,10 @@ analysis is eq. (2)-(3) in that basis with real coefficients:
 
 R_dst the eigenvalues of R in the sine basis (R = r I gives r everywhere) and
 e_hat_k = sqrt(R_dst) z_k with z real standard normals (the sine transform of
-white noise is white): z for DST bin (s1, s2) and member k is the first output
-of Box-Muller on words (x0, x1) of Philox4x32-10 if k is even, (x2, x3) if odd,
-key = (seed lo, seed hi), counter = (s1 * nx + s2, k div 2, 1, 0).
+white noise is white).  z for DST bin (s1, s2) and member k comes from
+Philox4x32-10 with key = (seed lo, seed hi) and counter = (s1 * nx + s2,
+k div 4, 1, 0): Box-Muller on words (x0, x1) gives members 4q and 4q + 1 (its
+cosine and sine outputs), on (x2, x3) members 4q + 2 and 4q + 3.
 """
 
 from __future__ import annotations
@@ -66,9 +67,9 @@ def dst_noise(seed: int, N: int, ny: int, nx: int) -> np.ndarray:
     bins = np.arange(ny * nx, dtype=np.uint64)
     z = np.empty((N, ny * nx))
     for k in range(N):
-        w = philox4x32((bins, np.uint64(k // 2), np.uint64(1), np.uint64(0)), key)
-        wa, wb = (w[0], w[1]) if k % 2 == 0 else (w[2], w[3])
-        z[k], _ = box_muller(wa, wb)
+        w = philox4x32((bins, np.uint64(k // 4), np.uint64(1), np.uint64(0)), key)
+        wa, wb = (w[0], w[1]) if k % 4 < 2 else (w[2], w[3])
+        z[k] = box_muller(wa, wb)[k % 2]
     return z.reshape(N, ny, nx)
 
 

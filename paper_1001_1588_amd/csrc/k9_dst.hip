@@ -44,17 +44,26 @@ template <typename T> __device__ __forceinline__ T tiny_t();
 template <> __device__ __forceinline__ float tiny_t<float>() { return 1.17549435e-38f; }
 template <> __device__ __forceinline__ double tiny_t<double>() { return 2.2250738585072014e-308; }
 
+// Index of V(ky, kx) of field 0 in the transformed layout of sweep 2; field f
+// is f * field_stride elements further.
 template <typename T>
-__device__ __forceinline__ V2<T>* spectrum_at(const K9Args& a, int f, int ky, int kx) {
+__device__ __forceinline__ V2<T>* spectrum_at(const K9Args& a, int ky, int kx) {
   const int nxh = a.nx / 2;
   const int k2 = ky % a.R, k1 = ky / a.R;
-  if (kx < nxh) return static_cast<V2<T>*>(a.ws_main) + (((size_t)f * a.R + k2) * a.L + k1) * nxh + kx;
-  return static_cast<V2<T>*>(a.ws_nyq) + ((size_t)f * a.L + k1) * a.R + k2;
+  if (kx < nxh) return static_cast<V2<T>*>(a.ws_main) + ((size_t)k2 * a.L + k1) * nxh + kx;
+  return static_cast<V2<T>*>(a.ws_nyq) + (size_t)k1 * a.R + k2;
 }
 
 // One thread per mirror set {a, n1-a} x {b, n2-b}, 0 <= a <= n1/2, 0 <= b <= n2/2.
+// The thread works on the unnormalised coefficients X = s / alpha: eq. (2)
+// takes alpha^2 var(X), and eq. (3) becomes
+//   X^a_k = X_k + g (X_d - X_k) + (g sqrt(R_dst) / alpha) z_k.
+// Perturbations: Philox counter (bin, k div 4, 1, 0) at DST bin (s1, s2), bin =
+// s1 * nx + s2; Box-Muller on words (x0, x1) gives members 4q and 4q + 1, on
+// (x2, x3) members 4q + 2 and 4q + 3.
 template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void dst_quad(const K9Args a) {
+  static_assert(NMAX % 4 == 0, "member bucket must be a multiple of 4");
   const int n1 = a.ny, n2 = a.nx;
   const int hb = n2 / 2 + 1;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,79 +72,86 @@ __global__ __launch_bounds__(256) void dst_quad(const K9Args a) {
   const int ma = (n1 - qa) % n1, mb = (n2 - qb) % n2;  // the mirror rows and columns
   const bool da = ma != qa, db = mb != qb;             // distinct mirror point
   const int N = a.N;
-  // the four points: 0 (qa, qb), 1 (ma, qb), 2 (qa, mb), 3 (ma, mb)
+  // the four points: 0 (qa, qb), 1 (ma, qb), 2 (qa, mb), 3 (ma, mb).  For a
+  // distinct mirror m = n - k, W(m) = -i conj W(k); a coinciding mirror point
+  // is never used.
+  const cx<T> w1 = wq<T>(qa, n1), w2 = wq<T>(qb, n2);
+  const cx<T> W1[4] = {w1, mul_mi(conj(w1)), w1, mul_mi(conj(w1))};
+  const cx<T> W2[4] = {w2, w2, mul_mi(conj(w2)), mul_mi(conj(w2))};
   const int pk1[4] = {qa, ma, qa, ma}, pk2[4] = {qb, qb, mb, mb};
-  cx<T> W1[4], W2[4];
+  const T r1 = sqrt(T(1) / T(n1)), r1b = sqrt(T(2) / T(n1)), r2 = sqrt(T(1) / T(n2)), r2b = sqrt(T(2) / T(n2));
   T alpha[4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    W1[p] = wq<T>(pk1[p], n1);
-    W2[p] = wq<T>(pk2[p], n2);
-    alpha[p] = sqrt((pk1[p] == 0 ? T(1) : T(2)) / T(n1)) * sqrt((pk2[p] == 0 ? T(1) : T(2)) / T(n2));
-  }
-  // X of every field at the four points (orthonormal sine coefficients)
-  // (member k in row k, d in row NMAX; padding rows are never read)
-  T s[NMAX + 1][4];
+  for (int p = 0; p < 4; ++p) alpha[p] = (pk1[p] == 0 ? r1 : r1b) * (pk2[p] == 0 ? r2 : r2b);
+  // the two stored points of every field
+  const size_t fstride = qb < n2 / 2 ? (size_t)a.R * a.L * (n2 / 2) : (size_t)a.L * a.R;
+  V2<T>* const va = spectrum_at<T>(a, qa, qb);
+  V2<T>* const vm = spectrum_at<T>(a, ma, qb);
+
+  // X of every field at the four points (member k in row k, d in row NMAX;
+  // padding rows are never read)
+  T X[NMAX + 1][4];
 #pragma unroll
   for (int f = 0; f <= NMAX; ++f) {
     if (f < N || f == NMAX) {
-      const int field = f == NMAX ? N : f;
-      const cx<T> Vab = from2<T>(*spectrum_at<T>(a, field, qa, qb));
-      const cx<T> Vmb = from2<T>(*spectrum_at<T>(a, field, ma, qb));
+      const size_t off = (size_t)(f == NMAX ? N : f) * fstride;
+      const cx<T> Vab = from2<T>(va[off]);
+      const cx<T> Vmb = from2<T>(vm[off]);
       // V at (qa, -qb) = conj V(ma, qb); at (ma, -qb) = conj V(qa, qb)
       const cx<T> Vp[4] = {Vab, Vmb, conj(Vmb), conj(Vab)};
       const cx<T> Vn[4] = {conj(Vmb), conj(Vab), Vab, Vmb};  // V at (k1, -k2) of each point
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         const cx<T> z = W1[p] * (W2[p] * Vp[p] + conj(W2[p]) * Vn[p]);
-        s[f][p] = T(0.5) * z.re * alpha[p];
+        X[f][p] = T(0.5) * z.re;
       }
     }
   }
   // eq. (2)-(3) at each distinct point; the DST bin is (n1-1-k1, n2-1-k2)
   const bool live[4] = {true, da, db, da && db};
   const T* __restrict__ Rd = static_cast<const T*>(a.R_dst);
+  const T invN = T(1) / T(N), invN1 = T(1) / T(N - 1);
   static_for<0, 4>([&](auto PI) __attribute__((always_inline)) {
     constexpr int p = decltype(PI)::value;
     if (!live[p]) return;
     const int s1 = n1 - 1 - pk1[p], s2 = n2 - 1 - pk2[p];
-    T mean = T(0);
-#pragma unroll
-    for (int f = 0; f < NMAX; ++f)
-      if (f < N) mean += s[f][p];
-    mean /= T(N);
-    T var = T(0);
-#pragma unroll
-    for (int f = 0; f < NMAX; ++f)
-      if (f < N) var += (s[f][p] - mean) * (s[f][p] - mean);
-    const T c = var / T(N - 1);
-    const T r = Rd != nullptr ? Rd[(size_t)s1 * n2 + s2] : T(a.r_scalar);
-    const T den = c + r;
-    const T gain = den < tiny_t<T>() ? T(0) : c / den;
-    const T amp = sqrt(r);
     if (a.dbg_coeffs != nullptr) {  // test export: the sine coefficients of every field
       T* dc = static_cast<T*>(a.dbg_coeffs);
       const size_t plane = (size_t)n1 * n2, bin = (size_t)s1 * n2 + s2;
 #pragma unroll
       for (int f = 0; f < NMAX; ++f)
-        if (f < N) dc[f * plane + bin] = s[f][p];
-      dc[N * plane + bin] = s[NMAX][p];
+        if (f < N) dc[f * plane + bin] = alpha[p] * X[f][p];
+      dc[N * plane + bin] = alpha[p] * X[NMAX][p];
       return;
     }
-    const uint32_t ctr0 = (uint32_t)(s1 * n2 + s2);
+    T mean = T(0);
 #pragma unroll
-    for (int q = 0; q < (NMAX + 1) / 2; ++q) {
-      if (2 * q < N) {
+    for (int f = 0; f < NMAX; ++f)
+      if (f < N) mean += X[f][p];
+    mean *= invN;
+    T var = T(0);
+#pragma unroll
+    for (int f = 0; f < NMAX; ++f)
+      if (f < N) var += (X[f][p] - mean) * (X[f][p] - mean);
+    const T c = alpha[p] * alpha[p] * var * invN1;
+    const T r = Rd != nullptr ? Rd[(size_t)s1 * n2 + s2] : T(a.r_scalar);
+    const T den = c + r;
+    const T g = den < tiny_t<T>() ? T(0) : c / den;
+    const T ge = g * sqrt(r) / alpha[p];
+    const T xd = X[NMAX][p];
+    const uint32_t ctr0 = (uint32_t)(s1 * n2 + s2);
+    static_for<0, NMAX / 4>([&](auto QI) __attribute__((always_inline)) {
+      constexpr int q = decltype(QI)::value;
+      if (4 * q < N) {
         const u32x4 w = philox4x32_10(u32x4{ctr0, (uint32_t)q, 1u, 0u}, a.key0, a.key1);
-        T za, zb;
-        box_muller<T>(w.x0, w.x1, za, zb);
-        s[2 * q][p] += gain * (s[NMAX][p] + amp * za - s[2 * q][p]);
-        if (2 * q + 1 < NMAX && 2 * q + 1 < N) {
-          box_muller<T>(w.x2, w.x3, za, zb);
-          s[2 * q + 1][p] += gain * (s[NMAX][p] + amp * za - s[2 * q + 1][p]);
-        }
+        T z[4];
+        box_muller<T>(w.x0, w.x1, z[0], z[1]);
+        if (4 * q + 2 < N) box_muller<T>(w.x2, w.x3, z[2], z[3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * q + j < N) X[4 * q + j][p] += g * (xd - X[4 * q + j][p]) + ge * z[j];
       }
-    }
+    });
   });
   if (a.dbg_coeffs != nullptr) return;
   // back to V at the two stored points (qa, qb) and (ma, qb); a mirror point
@@ -143,31 +159,28 @@ __global__ __launch_bounds__(256) void dst_quad(const K9Args a) {
 #pragma unroll
   for (int f = 0; f < NMAX; ++f) {
     if (f >= N) continue;
-    T X[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) X[p] = s[f][p] / alpha[p];
+    T Y[4] = {X[f][0], X[f][1], X[f][2], X[f][3]};
     if (!da) {
-      X[1] = X[0];
-      X[3] = X[2];
+      Y[1] = Y[0];
+      Y[3] = Y[2];
     }
     if (!db) {
-      X[2] = X[0];
-      X[3] = X[1];
+      Y[2] = Y[0];
+      Y[3] = Y[1];
     }
     // X at index n (a mirror of row or column 0) is zero
-    const T x_ab = X[0];
-    const T x_mr = qa == 0 ? T(0) : X[1];              // X(n1 - qa, qb)
-    const T x_mc = qb == 0 ? T(0) : X[2];              // X(qa, n2 - qb)
-    const T x_mm = (qa == 0 || qb == 0) ? T(0) : X[3];  // X(n1 - qa, n2 - qb)
-    const cx<T> Va = conj(W1[0] * W2[0]) * cx<T>{x_ab - x_mm, -(x_mr + x_mc)};
-    *spectrum_at<T>(a, f, qa, qb) = to2<T>(Va);
+    const T x_ab = Y[0];
+    const T x_mr = qa == 0 ? T(0) : Y[1];              // X(n1 - qa, qb)
+    const T x_mc = qb == 0 ? T(0) : Y[2];              // X(qa, n2 - qb)
+    const T x_mm = (qa == 0 || qb == 0) ? T(0) : Y[3];  // X(n1 - qa, n2 - qb)
+    const size_t off = (size_t)f * fstride;
+    va[off] = to2<T>(conj(W1[0] * W2[0]) * cx<T>{x_ab - x_mm, -(x_mr + x_mc)});
     if (da) {
       // for the point (ma, qb): X(n1 - ma, .) = X(qa, .), never at index n
-      const T y_ab = X[1], y_mr = X[0];
-      const T y_mc = qb == 0 ? T(0) : X[3];
-      const T y_mm = qb == 0 ? T(0) : X[2];
-      const cx<T> Vm = conj(W1[1] * W2[1]) * cx<T>{y_ab - y_mm, -(y_mr + y_mc)};
-      *spectrum_at<T>(a, f, ma, qb) = to2<T>(Vm);
+      const T y_ab = Y[1], y_mr = Y[0];
+      const T y_mc = qb == 0 ? T(0) : Y[3];
+      const T y_mm = qb == 0 ? T(0) : Y[2];
+      vm[off] = to2<T>(conj(W1[1] * W2[1]) * cx<T>{y_ab - y_mm, -(y_mr + y_mc)});
     }
   }
 }
@@ -181,7 +194,9 @@ hipError_t launch_quad(const K9Args& a, hipStream_t s) {
 
 hipError_t launch_quad_f32(const K9Args& a, hipStream_t s) {
   if (a.N <= 8) return launch_quad<float, 8>(a, s);
+  if (a.N <= 12) return launch_quad<float, 12>(a, s);
   if (a.N <= 16) return launch_quad<float, 16>(a, s);
+  if (a.N <= 20) return launch_quad<float, 20>(a, s);
   if (a.N <= 24) return launch_quad<float, 24>(a, s);
   return hipErrorInvalidValue;
 }

@@ -82,8 +82,10 @@ def test_single_sine_mode_scalar_kalman_and_limits():
 def test_noise_convention_statistics():
     z = dst.dst_noise(123, 6, 64, 64)
     assert abs(z.mean()) < 0.02 and abs(z.var() - 1) < 0.02
-    # members are independent and bins are white
-    assert abs(np.corrcoef(z[0].ravel(), z[1].ravel())[0, 1]) < 0.03
+    # members are uncorrelated (0, 1: the two outputs of one Box-Muller pair;
+    # 0, 2: the two pairs of one Philox call; 0, 4: different calls) and bins are white
+    for j in (1, 2, 3, 4, 5):
+        assert abs(np.corrcoef(z[0].ravel(), z[j].ravel())[0, 1]) < 0.03
     assert abs(np.corrcoef(z[0, :, :-1].ravel(), z[0, :, 1:].ravel())[0, 1]) < 0.03
     # a different stream from the periodic analysis' perturbations
     per = enkf.spectral_noise(123, 2, 64, 64)
