@@ -240,11 +240,34 @@ __device__ __forceinline__ int lds_pad(int idx) { return idx + (idx >> 3); }
 // Elements to allocate for n logical elements.
 __host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 3) + 1; }
 
+// LDS index of element e of the sequence held in column `off` of `stride`
+// columns, relative to the sequence's block: the padded layout above.
+struct PadLayout {
+  static __device__ __forceinline__ int index(int e, int stride, int off) { return lds_pad(e * stride + off); }
+};
+
+// Rows of W columns of B-byte elements, unpadded.  The G = 256 / (W B) rows
+// sharing one 256-byte line of banks are permuted: row e takes slot
+// (e xor (e >> 2)) mod G of its group.  After a radix-4 pass a half-wave
+// writes rows 4t + m for G consecutive t and reads rows t + const, and both
+// sets then fall on distinct banks.
+template <int W, int B>
+struct SwizzleLayout {
+  static constexpr int G = W * B >= 256 ? 1 : 256 / (W * B);
+  static constexpr int elems(int rows) { return rows * W; }
+  static __device__ __forceinline__ int index(int e, int, int off) {
+    if constexpr (G == 1)
+      return e * W + off;
+    else
+      return ((e & ~(G - 1)) + ((e ^ (e >> 2)) & (G - 1))) * W + off;
+  }
+};
+
 // All passes of a length-NFFT transform for NB sequences held in registers,
 // v[s][i] = element (t + TF i) of sequence s.  In LDS, sequence s occupies the
 // block [s * SEQP, (s + 1) * SEQP) and its element e sits at
-// lds_pad(e * elem_stride + lp.off) inside it (SEQP >= lds_padded_size of the
-// largest index), so the per-sequence part of every address is a constant.
+// Layout::index(e, elem_stride, lp.off) inside it (SEQP above the largest
+// index), so the per-sequence part of every address is a constant.
 // Every thread of the block must call this (it synchronises the block).
 //
 // LDS exchange: with buf1 == nullptr each exchange writes buf0, synchronises,
@@ -271,7 +294,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // WAVE = true: all TF threads of a sequence belong to one wave and the LDS
 // region they exchange through is private to that wave, so exchanges need no
 // block synchronisation (buf1 is then ignored).
-template <typename T, int NFFT, int P, int NS, int NB, int SEQP, bool WAVE = false>
+template <typename T, int NFFT, int P, int NS, int NB, int SEQP, bool WAVE = false, typename Layout = PadLayout>
 __device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, LdsPair& lp, int elem_stride,
                                            const V2<T>* __restrict__ tab) {
   if constexpr (NS < NFFT) {
@@ -305,7 +328,7 @@ __device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, LdsPair& lp
         const int o = (b / NS) * NS * RAD + (b % NS);
 #pragma unroll
         for (int m = 0; m < RAD; ++m) {
-          V2<T>* dst = lds + lds_pad((o + m * NS) * elem_stride + lp.off);
+          V2<T>* dst = lds + Layout::index(o + m * NS, elem_stride, lp.off);
 #pragma unroll
           for (int s = 0; s < NB; ++s) dst[s * SEQP] = to2<T>(v[s][q + m * Q]);
         }
@@ -313,7 +336,7 @@ __device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, LdsPair& lp
       if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        const V2<T>* src = lds + lds_pad((t + TF * i) * elem_stride + lp.off);
+        const V2<T>* src = lds + Layout::index(t + TF * i, elem_stride, lp.off);
 #pragma unroll
         for (int s = 0; s < NB; ++s) v[s][i] = from2<T>(src[s * SEQP]);
       }
@@ -323,25 +346,25 @@ __device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, LdsPair& lp
         __syncthreads();
       else
         lp.parity ^= 1;
-      fft_passes<T, NFFT, P, NS * RAD, NB, SEQP, WAVE>(v, t, lp, elem_stride, tab);
+      fft_passes<T, NFFT, P, NS * RAD, NB, SEQP, WAVE, Layout>(v, t, lp, elem_stride, tab);
     }
   }
 }
 
-template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false>
+template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false, typename Layout = PadLayout>
 __device__ __forceinline__ void fft_forward(cx<T> (&v)[NB][P], int t, LdsPair& lp, int elem_stride,
                                             const V2<T>* __restrict__ tab) {
-  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE>(v, t, lp, elem_stride, tab);
+  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE, Layout>(v, t, lp, elem_stride, tab);
 }
 
-template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false>
+template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false, typename Layout = PadLayout>
 __device__ __forceinline__ void fft_inverse(cx<T> (&v)[NB][P], int t, LdsPair& lp, int elem_stride,
                                             const V2<T>* __restrict__ tab) {
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll
     for (int i = 0; i < P; ++i) v[s][i] = swapri(v[s][i]);
-  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE>(v, t, lp, elem_stride, tab);
+  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE, Layout>(v, t, lp, elem_stride, tab);
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll

@@ -37,9 +37,14 @@ template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return 
 template <typename T>
 struct K2Geom {
   static constexpr int FB = sizeof(T) == 4 ? 4 : 2;  // fields per LDS round
-  // padded LDS block of one field: L rows of at most k2_threads_target * P / L columns
+  // columns of a full unit; a unit of fewer columns (narrow grids) leaves some unused
   template <int L>
-  static constexpr int seqp() { return lds_padded_size(k2_threads_target * k2_points(L)); }
+  static constexpr int cols() { return k2_threads_target * k2_points(L) / L; }
+  // LDS layout of one field's exchanges: L rows of cols() elements, swizzled
+  template <int L>
+  using Layout = SwizzleLayout<cols<L>(), (int)sizeof(V2<T>)>;
+  template <int L>
+  static constexpr int seqp() { return Layout<L>::elems(L); }
   template <int L>
   static constexpr size_t lds_bytes() { return 2 * (size_t)FB * seqp<L>() * sizeof(V2<T>); }
 };
@@ -109,6 +114,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   constexpr int TF2 = L / P;
   constexpr int FB = K2Geom<T>::FB;
   constexpr int SEQP = K2Geom<T>::template seqp<L>();
+  using Lay = typename K2Geom<T>::template Layout<L>;
   static_assert(NMAX % FB == 0 && FB % 2 == 0, "member bucket must be a multiple of the LDS batch");
   extern __shared__ unsigned char k2_lds_raw[];  // two buffers of FB fields
 
@@ -165,14 +171,14 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
-      fft_forward<T, L, P, FB, SEQP>(blk, t2, lp, C, tab);
+      fft_forward<T, L, P, FB, SEQP, false, Lay>(blk, t2, lp, C, tab);
 #pragma unroll
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) u[f0 + b][i] = blk[b][i];
     }
   }
-  fft_forward<T, L, P, 1, SEQP>(dv, t2, lp, C, tab);
+  fft_forward<T, L, P, 1, SEQP, false, Lay>(dv, t2, lp, C, tab);
   }
   const bool valid_w = valid;
 
@@ -286,7 +292,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
-      fft_inverse<T, L, P, FB, SEQP>(blk, t2, lp, C, tab);
+      fft_inverse<T, L, P, FB, SEQP, false, Lay>(blk, t2, lp, C, tab);
       if (valid) {
 #pragma unroll
         for (int b = 0; b < FB; ++b)

@@ -36,6 +36,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
   constexpr int TF2 = L / P;
   constexpr int FB = 2;  // fields per LDS round
   constexpr int SEQP = K2Geom<T>::template seqp<L>();
+  using Lay = typename K2Geom<T>::template Layout<L>;
   static_assert(NMAX % FB == 0, "member bucket must be a multiple of the LDS batch");
   extern __shared__ unsigned char k6_lds_raw[];  // two buffers of FB fields
 
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
         for (int b = 0; b < FB; ++b)
 #pragma unroll
           for (int i = 0; i < P; ++i) blk[b][i] = v[f0 + b][i];
-        fft_forward<T, L, P, FB, SEQP>(blk, t2, lp, C, tab);
+        fft_forward<T, L, P, FB, SEQP, false, Lay>(blk, t2, lp, C, tab);
 #pragma unroll
         for (int b = 0; b < FB; ++b)
 #pragma unroll
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
     for (int i = 0; i < P; ++i) dm[0][i] = from2<T>(ld_off(fb, voff[i]));
   }
   forward(del);
-  fft_forward<T, L, P, 1, SEQP>(dm, t2, lp, C, tab);
+  fft_forward<T, L, P, 1, SEQP, false, Lay>(dm, t2, lp, C, tab);
 
   const T n_tot = T(a.nx) * T(ny);
   const T invN = T(1) / T(N);
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
         for (int b = 0; b < FB; ++b)
 #pragma unroll
           for (int i = 0; i < P; ++i) blk[b][i] = v[f0 + b][i];
-        fft_inverse<T, L, P, FB, SEQP>(blk, t2, lp, C, tab);
+        fft_inverse<T, L, P, FB, SEQP, false, Lay>(blk, t2, lp, C, tab);
         if (g.valid) {
 #pragma unroll
           for (int b = 0; b < FB; ++b)
