@@ -249,8 +249,9 @@ bool log_enabled() {
 }
 
 // Enqueue sweeps 1 and 2 (mode) and, for an analysis, sweep 3.
-// With mlp, sweep 2 runs twice around the perceptron: K2_STATS, then (for an
-// analysis) K2_UPDATE_LEARNED; mlp_chat/mlp_lam/mlp_mu request the spectra only.
+// With mlp, sweep 2 runs twice around the perceptron: K2_CHAT (statistics
+// only), then (for an analysis) K2_ANALYZE with the perceptron's spectrum in
+// place of eq. (2); mlp_chat/mlp_lam/mlp_mu request the spectra only.
 int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_spec, uint64_t seed, void* out,
         int mode, void* dbg_chat, void* dbg_gain, void* dbg_spec, void* dbg_e, const fftenkf_mlp* mlp = nullptr,
         void* mlp_chat = nullptr, void* mlp_lam = nullptr, void* mlp_mu = nullptr, const void* lam = nullptr) {
@@ -306,7 +307,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   a2.tab = tab;
   if (mlp != nullptr) {
     // the perceptron needs c_hat of every bin, and their mean, before any update
-    a2.mode = K2_STATS;
+    a2.mode = K2_CHAT;
     a2.chat_map = mlp_chat != nullptr ? mlp_chat : ws + plan.off_chat;
     a2.partials = ws + plan.off_part;
     err = launch_k2_f32(a2, stream);
@@ -332,7 +333,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
     if (err == hipSuccess) err = mark(3, stream);
     if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "perceptron launch: %s", hipGetErrorString(err));
     if (mode != K2_ANALYZE) return FFTENKF_OK;
-    a2.mode = K2_UPDATE_LEARNED;
+    a2.mode = K2_ANALYZE;
     a2.lam_map = a7.lam;
     err = launch_k2_f32(a2, stream);
     if (err == hipSuccess) err = mark(4, stream);

@@ -104,9 +104,9 @@ __device__ __forceinline__ T sample_variance(const cx<T> (&u)[NMAX][P], int i, i
   return var * var_scale;
 }
 
-// SPLIT compiles the modes that start or stop at the transformed fields
-// (K2_STATS, K2_UPDATE_LEARNED, K2_INVERSE); the single-pass modes are compiled
-// without them.
+// SPLIT compiles the modes that stop or start at the transformed fields
+// (K2_STATS, K2_CHAT, K2_INVERSE); the single-pass modes are compiled without
+// them.
 // The work of one block; `unit` is its index within one analysis.
 template <typename T, int L, int NMAX, bool SPLIT>
 __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
@@ -161,7 +161,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   }
 
   // forward length-L transforms (the learned update starts from transformed fields)
-  const bool transformed = SPLIT && (a.mode == K2_UPDATE_LEARNED || a.mode == K2_INVERSE);
+  const bool transformed = SPLIT && a.mode == K2_INVERSE;
   if (!transformed) {
 #pragma unroll
   for (int f0 = 0; f0 < NMAX; f0 += FB) {
@@ -199,7 +199,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
     if (Rspec != nullptr && valid_w) rb = Rspec[(size_t)ky[i] * nh + kx];
     const T den = chat + rb;
     gain[i] = den < tiny_normal<T>() ? T(0) : chat / den;
-    if (SPLIT && a.mode == K2_STATS) {
+    if (SPLIT && (a.mode == K2_STATS || a.mode == K2_CHAT)) {
       if (valid_w) static_cast<T*>(a.chat_map)[(size_t)ky[i] * nh + kx] = chat;
       csum += valid_w ? chat : T(0);
     }
@@ -220,9 +220,9 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
     }
   }
   if (a.mode == K2_DEBUG_SPECTRA) return;  // no synchronisation follows
-  if (SPLIT && a.mode == K2_STATS) {
-    // transformed fields back in place, and this block's sum of c_hat
-    if (valid) {
+  if (SPLIT && (a.mode == K2_STATS || a.mode == K2_CHAT)) {
+    // transformed fields back in place (K2_STATS), and this block's sum of c_hat
+    if (valid && a.mode == K2_STATS) {
 #pragma unroll
       for (int f = 0; f < NMAX; ++f)
         if (f < N) {
@@ -352,7 +352,7 @@ hipError_t launch_k2_variant(const K2Args& a, hipStream_t st) {
 
 template <typename T, int L, int NMAX>
 hipError_t launch_k2_shape(const K2Args& a, hipStream_t st) {
-  const bool split = a.mode == K2_STATS || a.mode == K2_UPDATE_LEARNED || a.mode == K2_INVERSE;
+  const bool split = a.mode == K2_STATS || a.mode == K2_CHAT || a.mode == K2_INVERSE;
   if (split) return launch_k2_variant<T, L, NMAX, true>(a, st);
   return launch_k2_variant<T, L, NMAX, false>(a, st);
 }

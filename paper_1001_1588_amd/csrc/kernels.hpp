@@ -34,9 +34,10 @@ struct K1Args {
 // K2_STATS: forward transforms and eq. (2) only -- writes c_hat to chat_map,
 //   one partial sum of c_hat per block to partials, and the transformed fields
 //   back in place.
-// K2_UPDATE_LEARNED: starts from those transformed fields.
+// K2_CHAT: K2_STATS without writing the fields back (the learned analysis
+//   transforms them again in its K2_ANALYZE pass).
 // In any mode a non-null lam_map replaces eq. (2) in the gain: the covariance
-// eigenvalues are read from it (an estimate, or a prescribed spectrum).
+//   eigenvalues are read from it (an estimate, or a prescribed spectrum).
 // K2_INVERSE: starts from transformed fields and only applies the inverse
 //   length-L transforms (the c2r test export).
 enum K2Mode {
@@ -44,7 +45,7 @@ enum K2Mode {
   K2_DEBUG_SPECTRA = 1,
   K2_DEBUG_PERTURB = 2,
   K2_STATS = 3,
-  K2_UPDATE_LEARNED = 4,
+  K2_CHAT = 4,
   K2_INVERSE = 5
 };
 
