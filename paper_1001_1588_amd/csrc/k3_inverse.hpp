@@ -118,7 +118,11 @@ __device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, const
   if (active) {
     T* __restrict__ dst = out + (size_t)f * ny * NX + t;
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
+    for (int ii = 0; ii < P; ++ii) {
+      // with SINE, points i and P - 1 - i in turn: the even output columns of
+      // thread t and the odd ones of thread TF - 1 - t then share 128-byte lines
+      // written one step apart, so the L2 merges the halves before write-back
+      const int i = SINE ? ((ii & 1) ? P - 1 - (ii >> 1) : (ii >> 1)) : ii;
       cx<T> V[H + 1];
       V[0] = cx<T>{s[0][i].re, T(0)};
       V[H] = cx<T>{s[0][i].im, T(0)};
