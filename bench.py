@@ -62,7 +62,7 @@ class HipEvents:
 
 def sweep_bytes(N: int, ny: int, nx: int, s: int, rspec_array: bool) -> dict:
     """Algorithmic bytes per launch of each sweep: its inputs read once and its
-    outputs written once (measurement section)."""
+    outputs written once."""
     n = ny * nx
     half = ny * (nx // 2 + 1) * 2 * s          # one complex half spectrum
     rs = ny * (nx // 2 + 1) * s if rspec_array else 0
@@ -361,8 +361,8 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the analysis runs on a single MI355X in this build "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the analysis runs on a single MI355X (a multi-GPU "
+              "split of the grid rows is designed but not built); run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
