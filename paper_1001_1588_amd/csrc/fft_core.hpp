@@ -212,9 +212,11 @@ __host__ __device__ __forceinline__ void irdft(const cx<T>* V, T* a) {
 // ------------------------------------------------------------ Stockham passes
 // Twiddles W_M^(j m), m = 0..RAD-1, from the table; three table loads per radix-8
 // butterfly (W^j, W^2j, W^4j), the rest by products of at most two levels.
-template <typename T, int RAD>
+// `tab` holds W_TWN^k for k < TWN (the 4096-entry device table, or a block's
+// own copy of the TWN = NFFT twiddles in LDS); M divides TWN.
+template <typename T, int RAD, int TWN = kTwiddleN>
 __device__ __forceinline__ void load_twiddles(cx<T>* w, int j, int M, const V2<T>* __restrict__ tab) {
-  const int s = kTwiddleN / M;
+  const int s = TWN / M;
   w[0] = cx<T>{T(1), T(0)};
   if constexpr (RAD >= 2) w[1] = from2<T>(tab[j * s]);
   if constexpr (RAD >= 4) {
@@ -282,6 +284,16 @@ struct LdsPair {
   int off;  // per-thread element offset added to every index (e.g. a column)
 };
 
+// Block barrier that orders LDS only: every wave's earlier LDS accesses
+// complete before any wave passes it.  Unlike __syncthreads it does not wait
+// for the wave's outstanding global loads and stores, which the exchanges do
+// not need (every thread reads and writes its own global addresses).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Order a wave's own LDS writes before its later reads (and reads before later
 // writes) without a block-wide barrier: LDS instructions of one wave execute in
 // order, so only the compiler has to be kept from moving them.
@@ -294,7 +306,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // WAVE = true: all TF threads of a sequence belong to one wave and the LDS
 // region they exchange through is private to that wave, so exchanges need no
 // block synchronisation (buf1 is then ignored).
-template <typename T, int NFFT, int P, int NS, int NB, int SEQP, bool WAVE = false, typename Layout = PadLayout>
+template <typename T, int NFFT, int P, int NS, int NB, int SEQP, bool WAVE = false, typename Layout = PadLayout,
+          int TWN = kTwiddleN>
 __device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, LdsPair& lp, int elem_stride,
                                            const V2<T>* __restrict__ tab) {
   if constexpr (NS < NFFT) {
@@ -305,7 +318,7 @@ __device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, LdsPair& lp
     for (int q = 0; q < Q; ++q) {
       const int b = t + TF * q;
       cx<T> w[RAD];
-      if constexpr (NS > 1) load_twiddles<T, RAD>(w, b % NS, NS * RAD, tab);
+      if constexpr (NS > 1) load_twiddles<T, RAD, TWN>(w, b % NS, NS * RAD, tab);
 #pragma unroll
       for (int s = 0; s < NB; ++s) {
         cx<T> a[RAD];
@@ -333,7 +346,7 @@ __device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, LdsPair& lp
           for (int s = 0; s < NB; ++s) dst[s * SEQP] = to2<T>(v[s][q + m * Q]);
         }
       }
-      if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
+      if constexpr (WAVE) wave_lds_sync(); else lds_barrier();
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         const V2<T>* src = lds + Layout::index(t + TF * i, elem_stride, lp.off);
@@ -343,28 +356,30 @@ __device__ __forceinline__ void fft_passes(cx<T> (&v)[NB][P], int t, LdsPair& lp
       if constexpr (WAVE)
         wave_lds_sync();
       else if (lp.buf1 == nullptr)
-        __syncthreads();
+        lds_barrier();
       else
         lp.parity ^= 1;
-      fft_passes<T, NFFT, P, NS * RAD, NB, SEQP, WAVE, Layout>(v, t, lp, elem_stride, tab);
+      fft_passes<T, NFFT, P, NS * RAD, NB, SEQP, WAVE, Layout, TWN>(v, t, lp, elem_stride, tab);
     }
   }
 }
 
-template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false, typename Layout = PadLayout>
+template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false, typename Layout = PadLayout,
+          int TWN = kTwiddleN>
 __device__ __forceinline__ void fft_forward(cx<T> (&v)[NB][P], int t, LdsPair& lp, int elem_stride,
                                             const V2<T>* __restrict__ tab) {
-  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE, Layout>(v, t, lp, elem_stride, tab);
+  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE, Layout, TWN>(v, t, lp, elem_stride, tab);
 }
 
-template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false, typename Layout = PadLayout>
+template <typename T, int NFFT, int P, int NB, int SEQP, bool WAVE = false, typename Layout = PadLayout,
+          int TWN = kTwiddleN>
 __device__ __forceinline__ void fft_inverse(cx<T> (&v)[NB][P], int t, LdsPair& lp, int elem_stride,
                                             const V2<T>* __restrict__ tab) {
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll
     for (int i = 0; i < P; ++i) v[s][i] = swapri(v[s][i]);
-  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE, Layout>(v, t, lp, elem_stride, tab);
+  fft_passes<T, NFFT, P, 1, NB, SEQP, WAVE, Layout, TWN>(v, t, lp, elem_stride, tab);
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll

@@ -135,7 +135,7 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
   // 5. sequence 0: V_0^(m) = (S(m) + conj S(-m)) / 2, V_{R/2}^(m) = (S(m) - conj S(-m)) / 2i
 #pragma unroll
   for (int i = 0; i < P; ++i) my[lds_pad(t + TF * i)] = to2<T>(s[0][i]);
-  __syncthreads();
+  lds_barrier();
   if (active) {
     const cx<T> wh = twiddle<T>(tab, y1 * H, ny);
     V2<T>* __restrict__ row0 = ws_main + ((frow + 0) * L + y1) * NXH;

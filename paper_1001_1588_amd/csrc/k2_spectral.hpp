@@ -45,9 +45,21 @@ struct K2Geom {
   using Layout = SwizzleLayout<cols<L>(), (int)sizeof(V2<T>)>;
   template <int L>
   static constexpr int seqp() { return Layout<L>::elems(L); }
+  // two exchange buffers of FB fields, then the block's copy of W_L^k (k < L)
   template <int L>
-  static constexpr size_t lds_bytes() { return 2 * (size_t)FB * seqp<L>() * sizeof(V2<T>); }
+  static constexpr size_t lds_bytes() { return (2 * (size_t)FB * seqp<L>() + L) * sizeof(V2<T>); }
 };
+
+// The block's LDS copy of the twiddles W_L^k, k < L, of its length-L transforms.
+// Reading them from LDS rather than from the device table keeps the
+// transforms' waits off the vector-memory counter, which the loads and stores
+// of whole fields share: a twiddle load issued behind them would make every
+// pass wait for all of those to complete.
+template <typename T, int L>
+__device__ __forceinline__ const V2<T>* copy_twiddles(V2<T>* tw, const V2<T>* __restrict__ tab) {
+  for (int k = threadIdx.x; k < L; k += blockDim.x) tw[k] = tab[k * (kTwiddleN / L)];
+  return tw;
+}
 
 // The perturbation of one bin: Philox counter word 0 (the bin's canonical
 // index gy * (nx/2 + 1) + kx) and the scales of the real and imaginary parts.
@@ -116,7 +128,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   constexpr int SEQP = K2Geom<T>::template seqp<L>();
   using Lay = typename K2Geom<T>::template Layout<L>;
   static_assert(NMAX % FB == 0 && FB % 2 == 0, "member bucket must be a multiple of the LDS batch");
-  extern __shared__ unsigned char k2_lds_raw[];  // two buffers of FB fields
+  extern __shared__ unsigned char k2_lds_raw[];  // two buffers of FB fields, then W_L^k
 
   const V2<T>* __restrict__ tab = static_cast<const V2<T>*>(a.tab);
   const int C = a.C;
@@ -139,6 +151,8 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   for (int i = 0; i < P; ++i) voff[i] = ((uint32_t)(t2 + TF2 * i) * sy + (uint32_t)cc) * (uint32_t)sizeof(V2<T>);
   V2<T>* lds0 = reinterpret_cast<V2<T>*>(k2_lds_raw);
   LdsPair lp{lds0, lds0 + FB * SEQP, 0, c};
+  // the twiddles (visible to all threads after the first exchange's barrier)
+  const V2<T>* const tw = copy_twiddles<T, L>(lds0 + 2 * FB * SEQP, tab);
 
   // load: members into u, data into dv (first-pass layout)
   cx<T> u[NMAX][P];
@@ -160,7 +174,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
     for (int i = 0; i < P; ++i) dv[0][i] = from2<T>(ld_off(fb, voff[i]));
   }
 
-  // forward length-L transforms (the learned update starts from transformed fields)
+  // forward length-L transforms (the inverse-only mode starts from transformed fields)
   const bool transformed = SPLIT && a.mode == K2_INVERSE;
   if (!transformed) {
 #pragma unroll
@@ -171,14 +185,14 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
-      fft_forward<T, L, P, FB, SEQP, false, Lay>(blk, t2, lp, C, tab);
+      fft_forward<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
 #pragma unroll
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) u[f0 + b][i] = blk[b][i];
     }
   }
-  fft_forward<T, L, P, 1, SEQP, false, Lay>(dv, t2, lp, C, tab);
+  fft_forward<T, L, P, 1, SEQP, false, Lay, L>(dv, t2, lp, C, tw);
   }
   const bool valid_w = valid;
 
@@ -292,7 +306,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
-      fft_inverse<T, L, P, FB, SEQP, false, Lay>(blk, t2, lp, C, tab);
+      fft_inverse<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
       if (valid) {
 #pragma unroll
         for (int b = 0; b < FB; ++b)

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
   constexpr int SEQP = K2Geom<T>::template seqp<L>();
   using Lay = typename K2Geom<T>::template Layout<L>;
   static_assert(NMAX % FB == 0, "member bucket must be a multiple of the LDS batch");
-  extern __shared__ unsigned char k6_lds_raw[];  // two buffers of FB fields
+  extern __shared__ unsigned char k6_lds_raw[];  // two buffers of FB fields, then W_L^k
 
   const V2<T>* __restrict__ tab = static_cast<const V2<T>*>(a.tab);
   const int C = a.C;
@@ -56,6 +56,8 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
     voff[i] = ((uint32_t)(t2 + TF2 * i) * g.sy + (uint32_t)g.cc) * (uint32_t)sizeof(V2<T>);
   V2<T>* lds0 = reinterpret_cast<V2<T>*>(k6_lds_raw);
   LdsPair lp{lds0, lds0 + FB * SEQP, 0, c};
+  // the twiddles (visible to all threads after the first exchange's barrier)
+  const V2<T>* const tw = copy_twiddles<T, L>(lds0 + 2 * FB * SEQP, tab);
 
   auto field = [&](int f) -> V2<T>* { return g.ubase + (size_t)f * g.fstride; };
   // load the N members of block j (and zero the padding members)
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
         for (int b = 0; b < FB; ++b)
 #pragma unroll
           for (int i = 0; i < P; ++i) blk[b][i] = v[f0 + b][i];
-        fft_forward<T, L, P, FB, SEQP, false, Lay>(blk, t2, lp, C, tab);
+        fft_forward<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
 #pragma unroll
         for (int b = 0; b < FB; ++b)
 #pragma unroll
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
     for (int i = 0; i < P; ++i) dm[0][i] = from2<T>(ld_off(fb, voff[i]));
   }
   forward(del);
-  fft_forward<T, L, P, 1, SEQP, false, Lay>(dm, t2, lp, C, tab);
+  fft_forward<T, L, P, 1, SEQP, false, Lay, L>(dm, t2, lp, C, tw);
 
   const T n_tot = T(a.nx) * T(ny);
   const T invN = T(1) / T(N);
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
         for (int b = 0; b < FB; ++b)
 #pragma unroll
           for (int i = 0; i < P; ++i) blk[b][i] = v[f0 + b][i];
-        fft_inverse<T, L, P, FB, SEQP, false, Lay>(blk, t2, lp, C, tab);
+        fft_inverse<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
         if (g.valid) {
 #pragma unroll
           for (int b = 0; b < FB; ++b)
@@ -218,7 +220,7 @@ template <typename T, int L, int NMAX>
 hipError_t launch_k6_shape(const K6Args& a, hipStream_t st) {
   constexpr int P = k2_points(L);
   const dim3 grid(a.units_total), block(a.C * (L / P));
-  constexpr size_t lds_bytes = 2 * 2 * (size_t)K2Geom<T>::template seqp<L>() * sizeof(V2<T>);
+  constexpr size_t lds_bytes = (2 * 2 * (size_t)K2Geom<T>::template seqp<L>() + L) * sizeof(V2<T>);
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k6_multiblock<T, L, NMAX>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (attr != hipSuccess) return attr;
