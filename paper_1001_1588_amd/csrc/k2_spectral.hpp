@@ -36,7 +36,11 @@ template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return 
 
 template <typename T>
 struct K2Geom {
-  static constexpr int FB = sizeof(T) == 4 ? 4 : 2;  // fields per LDS round
+  // fields per LDS round: four for float32 buckets above 8 members (two waves
+  // per SIMD at most, by registers); two for smaller buckets, whose registers
+  // allow three or four waves per SIMD if the exchange buffers leave room
+  template <int NMAX>
+  static constexpr int fb() { return sizeof(T) == 4 && NMAX > 8 ? 4 : 2; }
   // columns of a full unit; a unit of fewer columns (narrow grids) leaves some unused
   template <int L>
   static constexpr int cols() { return k2_threads_target * k2_points(L) / L; }
@@ -45,9 +49,9 @@ struct K2Geom {
   using Layout = SwizzleLayout<cols<L>(), (int)sizeof(V2<T>)>;
   template <int L>
   static constexpr int seqp() { return Layout<L>::elems(L); }
-  // two exchange buffers of FB fields, then the block's copy of W_L^k (k < L)
-  template <int L>
-  static constexpr size_t lds_bytes() { return (2 * (size_t)FB * seqp<L>() + L) * sizeof(V2<T>); }
+  // two exchange buffers of fb() fields, then the block's copy of W_L^k (k < L)
+  template <int L, int NMAX>
+  static constexpr size_t lds_bytes() { return (2 * (size_t)fb<NMAX>() * seqp<L>() + L) * sizeof(V2<T>); }
 };
 
 // The block's LDS copy of the twiddles W_L^k, k < L, of its length-L transforms.
@@ -124,7 +128,7 @@ template <typename T, int L, int NMAX, bool SPLIT>
 __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   constexpr int P = k2_points(L);
   constexpr int TF2 = L / P;
-  constexpr int FB = K2Geom<T>::FB;
+  constexpr int FB = K2Geom<T>::template fb<NMAX>();
   constexpr int SEQP = K2Geom<T>::template seqp<L>();
   using Lay = typename K2Geom<T>::template Layout<L>;
   static_assert(NMAX % FB == 0 && FB % 2 == 0, "member bucket must be a multiple of the LDS batch");
@@ -344,7 +348,7 @@ template <typename T, int L, int NMAX>
 hipError_t launch_k2_batch_shape(const BatchArgs& b, hipStream_t st) {
   constexpr int P = k2_points(L);
   const dim3 grid(b.k2.units_total, b.count), block(b.k2.C * (L / P));
-  constexpr size_t lds_bytes = K2Geom<T>::template lds_bytes<L>();
+  constexpr size_t lds_bytes = K2Geom<T>::template lds_bytes<L, NMAX>();
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_spectral_batch<T, L, NMAX>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (attr != hipSuccess) return attr;
@@ -356,7 +360,7 @@ template <typename T, int L, int NMAX, bool SPLIT>
 hipError_t launch_k2_variant(const K2Args& a, hipStream_t st) {
   constexpr int P = k2_points(L);
   const dim3 grid(a.units_total), block(a.C * (L / P));
-  constexpr size_t lds_bytes = K2Geom<T>::template lds_bytes<L>();
+  constexpr size_t lds_bytes = K2Geom<T>::template lds_bytes<L, NMAX>();
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_spectral<T, L, NMAX, SPLIT>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (attr != hipSuccess) return attr;
