@@ -24,11 +24,12 @@
 
 namespace fftenkf {
 
-// Two member sets per thread: up to 4 float members fit two waves per SIMD,
-// larger buckets run one wave per SIMD with their registers spread over the
-// unified file instead of spilling.
+// Two member sets per thread.  Buckets of up to 10 float members run two waves
+// per SIMD (at 10 members that spills about 50 registers, and is still faster
+// than one wave: 172 vs 185 us at 4 x 1024^2); larger buckets run one wave per
+// SIMD with their registers spread over the unified file instead of spilling.
 template <typename T, int NMAX>
-constexpr int k6_waves() { return NMAX * (int)sizeof(T) <= 16 ? 2 : 1; }
+constexpr int k6_waves() { return NMAX * (int)sizeof(T) <= 40 ? 2 : 1; }
 
 template <typename T, int L, int NMAX>
 __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_multiblock(const K6Args a) {
