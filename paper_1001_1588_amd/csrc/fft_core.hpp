@@ -398,6 +398,21 @@ __device__ __forceinline__ void st_off(V* base, uint32_t byte_off, V v) {
   *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// Loads of data read once: the nontemporal hint lets the caches stream them
+// instead of keeping lines no one will read again.
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  const nt_float2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float ld_stream(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+
 // Table entry W_M^k (forward) for M dividing 4096 and 0 <= k < M.
 template <typename T>
 __device__ __forceinline__ cx<T> twiddle(const V2<T>* __restrict__ tab, int k, int M) {

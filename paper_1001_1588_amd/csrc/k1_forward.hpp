@@ -50,7 +50,7 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
   V2<T>* my = lds + g * SB * SEQP;
   LdsPair lp{my, nullptr, 0, 0};
 
-  // 1. the R rows at this thread's x positions
+  // 1. the R rows at this thread's x positions (read once: streaming loads)
   T a[R][P];
 #pragma unroll
   for (int y2 = 0; y2 < R; ++y2) {
@@ -65,13 +65,15 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
       for (int i = 0; i < P; ++i) {
         const int j2 = t + TF * i;
         const uint32_t i2 = (uint32_t)(i < P / 2 ? 2 * j2 : 2 * (NX - 1 - j2) + 1);
-        const T x = active ? ld_off(src, rowoff + i2 * (uint32_t)sizeof(T)) : T(0);
+        const T x = active ? ld_stream(reinterpret_cast<const T*>(reinterpret_cast<const char*>(src) + rowoff +
+                                                                   i2 * (uint32_t)sizeof(T)))
+                           : T(0);
         a[y2][i] = ((y2 >= R / 2) != (i >= P / 2)) ? -x : x;
       }
     } else {
       const T* __restrict__ row = src + (size_t)(y1 + L * y2) * NX + t;
 #pragma unroll
-      for (int i = 0; i < P; ++i) a[y2][i] = active ? row[TF * i] : T(0);
+      for (int i = 0; i < P; ++i) a[y2][i] = active ? ld_stream(row + TF * i) : T(0);
     }
   }
 
