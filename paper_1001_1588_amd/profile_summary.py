@@ -4,7 +4,8 @@ Input: one directory holding three rocprofv3 outputs of bench.py,
   trace/  (--kernel-trace --stats, csv)   per-dispatch durations
   fetch/  (--pmc FETCH_SIZE, csv)         KiB fetched from HBM per dispatch
   write/  (--pmc WRITE_SIZE, csv)         KiB written to HBM per dispatch
-Kernels are keyed by name and grid size (one kernel serves several workloads).
+Kernels are keyed by name and grid size (one kernel serves several workloads);
+only the library's kernels and the copy reference are kept.
 Each byte counter is scaled by what it reads for bench.py's plain device copy
 of known size (the `__amd_rocclr_copyBuffer` dispatch, 2 x copy-mib MiB moved):
 the scale turns counter units into bytes.  Writes a JSON record (bench.py reads
@@ -87,6 +88,8 @@ def summarise(base: str, copy_mib: int) -> dict:
     scale = {kind: ((copy_bytes / 2) / copy_max[kind] if copy_max[kind] else None) for kind in ("fetch", "write")}
     kernels = []
     for (name, grid), d in sorted(durs.items(), key=lambda kv: -sum(kv[1])):
+        if not (name.startswith("fftenkf::") or name == COPY):
+            continue  # the benchmark's own torch and rocFFT kernels (input generation)
         fam = family(name)
         rec = {"name": name, "grid": grid, "calls": len(d), "avg_ns": sum(d) / len(d),
                "min_ns": min(d), "max_ns": max(d)}
