@@ -197,7 +197,8 @@ int fftenkf_analyze_batch(int n_members, int dtype, const fftenkf_filter* filter
  * fftenkf_set_tile_rows chooses one for every later call on that grid and
  * dtype in this process (0 restores the default; FFTENKF_EUNSUPPORTED if not
  * compiled); fftenkf_tile_rows returns the R in use.  The workspace size
- * depends on R: query it after choosing.
+ * depends on R: query it after choosing.  Default: R = 16 for float32 grids
+ * 2048 wide, else 8 (float64: 8, or 4 for grids 4096 wide), at most ny.
  */
 int fftenkf_tile_rows_options(int ny, int nx, int dtype, int* rows, int capacity);
 int fftenkf_set_tile_rows(int ny, int nx, int dtype, int rows);

@@ -200,9 +200,9 @@ def test_batch_validation_and_tuning(built_lib):
     assert lib.fftenkf_tile_rows_options(256, 256, 0, buf, 4) == 2 and list(buf[:2]) == [8, 16]
     assert lib.fftenkf_tile_rows_options(8, 64, 0, buf, 4) == 1 and buf[0] == 8       # R <= ny
     assert lib.fftenkf_tile_rows_options(64, 4096, 0, buf, 4) == 1 and buf[0] == 8
-    assert lib.fftenkf_tile_rows(256, 256, 0) == 16
-    assert lib.fftenkf_set_tile_rows(256, 256, 0, 8) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 8
-    assert lib.fftenkf_set_tile_rows(256, 256, 0, 0) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 16
+    assert lib.fftenkf_tile_rows(256, 256, 0) == 8 and lib.fftenkf_tile_rows(2048, 2048, 0) == 16
+    assert lib.fftenkf_set_tile_rows(256, 256, 0, 16) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 16
+    assert lib.fftenkf_set_tile_rows(256, 256, 0, 0) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 8
     assert lib.fftenkf_set_tile_rows(256, 256, 0, 4) == _lib.EUNSUPPORTED
 
 
