@@ -61,6 +61,12 @@ CASES = [
     (1024, 32, 17, np.float32, "spectral"),
     (8, 2048, 2, np.float32, "scalar"),
     (2048, 8, 6, np.float64, "scalar"),
+    # the extreme aspect ratios and sizes: 4096-wide rows (8-row tiles), 4096
+    # tall columns, the largest float32 bucket on a tall grid
+    (8, 4096, 3, np.float32, "spectral"),
+    (4096, 8, 4, np.float64, "scalar"),
+    (4096, 16, 24, np.float32, "spectral"),
+    (16, 4096, 8, np.float64, "spectral"),
 ]
 
 
