@@ -32,7 +32,9 @@ def method(ny, nx):
 
 CASES = [(8, 8, 2, np.float32), (8, 16, 3, np.float64), (16, 8, 4, np.float32), (32, 64, 5, np.float32),
          (64, 64, 6, np.float64), (128, 64, 20, np.float32), (64, 256, 24, np.float32), (256, 256, 8, np.float32),
-         (512, 128, 12, np.float32), (32, 2048, 3, np.float32)]
+         (512, 128, 12, np.float32), (32, 2048, 3, np.float32),
+         # 4096-wide rows (8-row tiles) and a tall float64 grid
+         (8, 4096, 3, np.float32), (2048, 16, 8, np.float64)]
 
 
 def case_id(c):
