@@ -82,8 +82,10 @@ def analyze_dst(ens, data, R_dst, seed: int, *, tiny=None, return_parts: bool = 
     R_dst = np.broadcast_to(np.asarray(R_dst, dtype=np.float64), (ny, nx))
     s_hat = dst2(ens.astype(np.float64), method)
     d_hat = dst2(np.asarray(data, dtype=np.float64), method)
-    mean = s_hat.mean(axis=0)
-    c_hat = ((s_hat - mean) ** 2).sum(axis=0) / (N - 1)
+    # eq. (2) on the coefficients taken relative to the first member (the same
+    # in exact arithmetic, exactly zero for a collapsed ensemble)
+    rel = s_hat - s_hat[0:1]
+    c_hat = ((rel - rel.mean(axis=0)) ** 2).sum(axis=0) / (N - 1)
     K = spectral_gain(c_hat, R_dst, tiny)
     e_hat = np.sqrt(R_dst)[None] * dst_noise(seed, N, ny, nx)
     sa = s_hat + K[None] * (d_hat[None] + e_hat - s_hat)

@@ -96,12 +96,19 @@ def spectral_perturbations(seed: int, N: int, R_spec: np.ndarray, nx: int) -> np
 # ------------------------------------------------------------- O1, spectral
 
 def spectral_mean_variance(u_hat: np.ndarray):
-    """Eq. (2): mean_i and c_hat_i over the member axis 0 of u_hat[N, ...]."""
+    """Eq. (2): mean_i and c_hat_i over the member axis 0 of u_hat[N, ...].
+
+    The squared deviations of eq. (2) are summed over s_k = u_hat_k - u_hat_1,
+    the members taken relative to the first one: subtracting a common value
+    changes neither the deviations from the mean nor c_hat in exact arithmetic,
+    and it makes c_hat exactly zero when every member is the same (a collapsed
+    ensemble, whose gain eq. (3) then guards), which the plain mean need not."""
     N = u_hat.shape[0]
     if N < 2:
         raise ValueError("eq. (2) needs N >= 2")
     mean = u_hat.sum(axis=0) / N
-    dev = u_hat - mean[None]
+    s = u_hat - u_hat[0:1]
+    dev = s - s.sum(axis=0, keepdims=True) / N
     c_hat = (dev.real ** 2 + dev.imag ** 2).sum(axis=0) / (N - 1)
     return mean, c_hat
 

@@ -16,6 +16,8 @@ Conventions (shared with the HIP kernels by specification only):
 * feature 25: log(1 + |k|), |k| = sqrt(ky'^2 + kx^2), ky' = min(ky, ny - ky);
 * layers: h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), h3 = relu(h2 W3 + b3),
   y = h3 . w4 + b4; lambda_hat = mu exp(y);
+* fallback: where mu is not a positive normal float32 the features do not
+  exist and lambda_hat is the plain c_hat;
 * precision: inputs, weights and the hidden activations that feed a product
   are rounded to bfloat16 (round to nearest, ties to even); products are
   accumulated in float64 here (float32 on the GPU); biases stay float32.
@@ -30,6 +32,8 @@ from .enkf import spectral_gain, spectral_mean_variance, spectral_perturbations,
 
 N_FEATURES = 26
 EPS = 1e-6
+MU_MIN = float(np.finfo(np.float32).tiny)  # smallest positive normal float32
+MU_MAX = float(np.finfo(np.float32).max)
 
 
 def round_bf16(x) -> np.ndarray:
@@ -86,9 +90,16 @@ def mlp(x: np.ndarray, w: dict, bf16: bool = True) -> np.ndarray:
 
 
 def learned_spectrum(c_half: np.ndarray, nx: int, w: dict, bf16: bool = True):
-    """(lambda_hat [ny, nx/2+1], mu) from a sample spectrum c_half."""
+    """(lambda_hat [ny, nx/2+1], mu) from a sample spectrum c_half.
+
+    The features divide by mu, so they exist only for a positive normal mu (in
+    float32, the precision of the kernels); otherwise -- an ensemble without
+    spread, or an overflowing one -- the estimate falls back to the plain
+    sample spectrum, lambda_hat = c_hat."""
     c_half = np.asarray(c_half, dtype=np.float64)
     mu = float(c_half.mean())
+    if not (MU_MIN <= mu <= MU_MAX):
+        return c_half.copy(), mu
     y = mlp(features(c_half, nx, mu), w, bf16=bf16)
     return mu * np.exp(y), mu
 

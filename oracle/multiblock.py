@@ -36,8 +36,12 @@ from .enkf import spectral_gain, spectral_perturbations, tiny_for
 def cross_spectrum(u_hat_j: np.ndarray, u_hat_1: np.ndarray) -> np.ndarray:
     """c_hat^(j1) [ny, nx/2+1] from the unitary spectra [N, ny, nx/2+1] of blocks j and 1."""
     N = u_hat_j.shape[0]
-    dj = u_hat_j - u_hat_j.mean(axis=0, keepdims=True)
-    d1 = u_hat_1 - u_hat_1.mean(axis=0, keepdims=True)
+    # deviations from the member mean, each block taken relative to its first
+    # member first (the same in exact arithmetic; exactly zero for a collapsed block)
+    sj = u_hat_j - u_hat_j[0:1]
+    s1 = u_hat_1 - u_hat_1[0:1]
+    dj = sj - sj.mean(axis=0, keepdims=True)
+    d1 = s1 - s1.mean(axis=0, keepdims=True)
     return (dj * np.conj(d1)).sum(axis=0) / (N - 1)
 
 

@@ -15,7 +15,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["test_oracle_dft.py", "test_oracle_variance.py", "test_oracle_update.py", "test_oracle_rng.py",
-             "test_oracle_learned.py", "test_oracle_multiblock.py", "test_oracle_dst.py"]
+             "test_oracle_learned.py", "test_oracle_multiblock.py", "test_oracle_dst.py",
+             "test_oracle_degenerate.py"]
 
 MUTANTS = [
     ("enkf.py", "sum(axis=0) / (N - 1)", "sum(axis=0) / N"),
@@ -43,7 +44,7 @@ MUTANTS = [
      "G = np.where(den < tiny, 0.0, cj1 / np.where(den < tiny, 1.0, c11))"),
     ("dst.py", "    S[n - 1] /= np.sqrt(2.0)\n", "\n"),
     ("dst.py", "(2 * j + 1) * (k + 1) / (2 * n)", "(2 * j + 1) * k / (2 * n)"),
-    ("dst.py", "((s_hat - mean) ** 2).sum(axis=0) / (N - 1)", "((s_hat - mean) ** 2).sum(axis=0) / N"),
+    ("dst.py", "((rel - rel.mean(axis=0)) ** 2).sum(axis=0) / (N - 1)", "((rel - rel.mean(axis=0)) ** 2).sum(axis=0) / N"),
     ("dst.py", "return dst2_matrix(ny).T @ s @ dst2_matrix(nx)", "return dst2_matrix(ny) @ s @ dst2_matrix(nx).T"),
     ("learned.py", "full[:, kx] = c_half[ky, nx - kx]", "full[:, kx] = c_half[:, nx - kx]"),
     ("learned.py", "dy, dx = j // 5 - 2, j % 5 - 2", "dx, dy = j // 5 - 2, j % 5 - 2"),
@@ -53,6 +54,14 @@ MUTANTS = [
     ("learned.py", "h = np.maximum(h @ W + b, 0.0)", "h = np.maximum(h @ W.T + b, 0.0)"),
     ("learned.py", "return mu * np.exp(y), mu", "return np.exp(y), mu"),
     ("learned.py", "K = spectral_gain(lam, R_spec, tiny)", "K = spectral_gain(c_hat, R_spec, tiny)"),
+    ("learned.py", "if not (MU_MIN <= mu <= MU_MAX):", "if False:"),
+    ("enkf.py", "s = u_hat - u_hat[0:1]", "s = u_hat"),
+    ("enkf.py", "safe = np.where(den < tiny, 1.0, den)\n    return np.where(den < tiny, 0.0, c_hat / safe)",
+     "return c_hat / den"),
+    # centring either factor suffices (the other's deviations sum to zero), so
+    # the plausible mistake is forgetting both
+    ("multiblock.py", "dj = sj - sj.mean(axis=0, keepdims=True)\n    d1 = s1 - s1.mean(axis=0, keepdims=True)",
+     "dj = sj\n    d1 = s1"),
 ]
 
 
