@@ -24,8 +24,10 @@
  * Philox4x32-10 (Salmon et al., SC'11), key = (seed mod 2^32, seed div 2^32),
  * counter = (gy * (nx/2 + 1) + gx, k div 2, 0, 0) for the generating bin
  * (gy, gx); member k takes words (x0, x1) if k is even, (x2, x3) if odd.
- * The gain is 0 where c_hat + R_spec is below the smallest normal number of the
- * working precision (no spread and no data error: no update).
+ * The squared deviations of eq. (2) are formed from u_hat_k - u_hat_0, the
+ * same sum in exact arithmetic, so c_hat is exactly 0 when all members are
+ * equal; the gain is 0 where c_hat + R_spec is below the smallest normal number
+ * of the working precision (no spread and no data error: no update).
  *
  * Layouts (row-major, x fastest):
  *   members / out : [N][ny][nx]  real, dtype        (device memory)
@@ -34,6 +36,8 @@
  *                   to use ens->r_scalar for every bin.  Values must be >= 0
  *                   and finite; in the kx = 0 and kx = nx/2 columns R_spec must
  *                   be even in ky (it is the spectrum of a real symmetric R).
+ *                   r_scalar (used when R_spec is NULL) must be >= 0 and finite
+ *                   in the working precision, else FFTENKF_EINVAL.
  * All device pointers must be 16-byte aligned; the workspace 256-byte aligned.
  *
  * Ownership: the caller owns every buffer.  The library keeps only per-device
@@ -106,7 +110,9 @@ size_t fftenkf_workspace_bytes(int n_members, int ny, int nx, int dtype);
  * y = h3 . w4 + b4 and lambda_hat = mu exp(y), mu = mean of c_hat over the
  * ny*(nx/2+1) stored bins.  The gain is lambda_hat / (lambda_hat + R_spec).
  * Inputs, weights and hidden activations are rounded to bfloat16 (nearest,
- * ties to even); products accumulate in float32 on the matrix cores.
+ * ties to even); products accumulate in float32 on the matrix cores.  Where mu
+ * is not a positive normal float (no spread anywhere) the features do not
+ * exist and lambda_hat falls back to the plain c_hat.
  * All eight pointers are device float32 arrays, row-major [in][out].
  */
 typedef struct fftenkf_mlp {
@@ -205,17 +211,19 @@ int fftenkf_set_tile_rows(int ny, int nx, int dtype, int rows);
 int fftenkf_tile_rows(int ny, int nx, int dtype);
 
 /*
- * The analysis in the real sine basis (Section 4: the sine transform forces
- * zero change on the boundary).  The transform is the orthonormal 2D DST-II,
+ * The analysis in the real sine basis (Section 4, whose experiment uses a sine
+ * transform so that the analysis leaves the boundary values unchanged).  The
+ * transform is the orthonormal 2D DST-II,
  *   S[k][j] = sqrt(2/n) c_k sin(pi (2j + 1)(k + 1) / (2n)),  c_{n-1} = 1/sqrt(2), else 1,
  * per axis, whose basis functions vanish at the cell faces j = -1/2, n - 1/2;
  * eq. (2) and eq. (3) act on its real coefficients:
  *   c_hat = 1/(N-1) sum_k (s_hat_k - mean)^2,
  *   s_hat_k^a = s_hat_k + c_hat / (c_hat + R_dst) (d_hat + e_hat_k - s_hat_k),
- * and the analysis is S^T s_hat_k^a.  e_hat_k = sqrt(R_dst) z with z the first
- * output of Box-Muller on words (x0, x1) of Philox4x32-10 for even k, (x2, x3)
- * for odd k, key as for fftenkf_analyze, counter = (s1 * nx + s2, k div 2, 1, 0)
- * for the sine bin (s1, s2).
+ * and the analysis is S^T s_hat_k^a.  e_hat_k = sqrt(R_dst) z with z drawn per
+ * sine bin (s1, s2) from Philox4x32-10, key as for fftenkf_analyze, counter
+ * (s1 * nx + s2, k div 4, 1, 0): Box-Muller on words (x0, x1) gives members
+ * 4q and 4q + 1 (its cosine and its sine output), on words (x2, x3) members
+ * 4q + 2 and 4q + 3, where q = k div 4.
  *   R_dst : device [ny][nx] real, the eigenvalues of R in the sine basis (>= 0),
  *           or NULL to use ens->r_scalar;
  *   workspace : fftenkf_workspace_bytes_dst(N, ny, nx, dtype) bytes.

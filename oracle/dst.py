@@ -2,8 +2,9 @@
 
 Test infrastructure only: the library never imports this module.
 
-The paper's experiment replaces the periodic DFT by the real sine transform,
-which forces zero change on the boundary.  Here that transform is the
+In its experiment (Section 4) the paper uses a real sine transform in place of
+the periodic DFT, so that the analysis leaves the boundary values unchanged.
+Here that transform is the
 orthonormal DST-II on an n-point grid,
 
    S[k, j] = sqrt(2/n) c_k sin(pi (2 j + 1) (k + 1) / (2 n)),   c_{n-1} = 1/sqrt(2), else 1,

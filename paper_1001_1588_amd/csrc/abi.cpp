@@ -191,6 +191,17 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 bool misaligned(const void* p, size_t a) { return ((uintptr_t)p % a) != 0; }
 
+// R = r I when no R_spec array is given: r must be >= 0 and finite in the
+// working precision (an infinite r would make the perturbation amplitude
+// infinite where the gain is exactly 0, and 0 * inf is NaN).
+int check_r_scalar(double r, int dtype, const char* prefix) {
+  const double rmax = dtype == FFTENKF_F32 ? (double)3.4028234663852886e+38 : 1.7976931348623157e+308;
+  if (!(r >= 0.0) || !(r <= rmax))
+    return fail(FFTENKF_EINVAL, "%sr_scalar = %g: it must be >= 0 and finite in the working precision when R_spec is NULL",
+                prefix, r);
+  return FFTENKF_OK;
+}
+
 // Shape, dtype, N and workspace checks common to every entry point.
 int validate_shape(const fftenkf_ens* e, Plan* plan) {
   if (e == nullptr) return fail(FFTENKF_EINVAL, "ens is NULL");
@@ -539,8 +550,12 @@ int validate_filter(const fftenkf_filter& f, int N, int dtype, int i, Plan* plan
   if (misaligned(f.members, 16) || misaligned(f.data, 16) || misaligned(f.out, 16) ||
       (f.R_spec != nullptr && misaligned(f.R_spec, 16)) || misaligned(f.workspace, 256))
     return fail(FFTENKF_EINVAL, "filter %d: pointers must be 16-byte (workspace 256-byte) aligned", i);
-  if (f.R_spec == nullptr && !(f.r_scalar >= 0.0))
-    return fail(FFTENKF_EINVAL, "filter %d: r_scalar must be >= 0 when R_spec is NULL", i);
+  if (f.R_spec == nullptr) {
+    char prefix[32];
+    snprintf(prefix, sizeof(prefix), "filter %d: ", i);
+    const int st = check_r_scalar(f.r_scalar, dtype, prefix);
+    if (st != FFTENKF_OK) return st;
+  }
   return FFTENKF_OK;
 }
 
@@ -696,8 +711,7 @@ int analyze_impl(const fftenkf_ens* e, const void* data, const void* R_spec, uin
     if (out == nullptr) return fail(FFTENKF_EINVAL, "out is NULL");
     if (misaligned(data, 16) || misaligned(out, 16) || (R_spec != nullptr && misaligned(R_spec, 16)))
       return fail(FFTENKF_EINVAL, "data, R_spec and out must be 16-byte aligned");
-    if (R_spec == nullptr && !(e->r_scalar >= 0.0))
-      return fail(FFTENKF_EINVAL, "r_scalar must be >= 0 when R_spec is NULL");
+    if (R_spec == nullptr && (st = check_r_scalar(e->r_scalar, e->dtype, "")) != FFTENKF_OK) return st;
     const size_t s = dsize(e->dtype);
     const size_t field = (size_t)e->ny * e->nx * s;
     const size_t ens_b = field * e->n_members;
@@ -938,8 +952,7 @@ int fftenkf_analyze_multi(const fftenkf_ens* e, int n_blocks, const void* data, 
     if (out == nullptr) return fail(FFTENKF_EINVAL, "out is NULL");
     if (misaligned(data, 16) || misaligned(out, 16) || (R_spec != nullptr && misaligned(R_spec, 16)))
       return fail(FFTENKF_EINVAL, "data, R_spec and out must be 16-byte aligned");
-    if (R_spec == nullptr && !(e->r_scalar >= 0.0))
-      return fail(FFTENKF_EINVAL, "r_scalar must be >= 0 when R_spec is NULL");
+    if (R_spec == nullptr && (st = check_r_scalar(e->r_scalar, e->dtype, "")) != FFTENKF_OK) return st;
     const size_t s = dsize(e->dtype);
     const size_t field = (size_t)e->ny * e->nx * s;
     const size_t ens_b = field * e->n_members * n_blocks;
@@ -1072,7 +1085,7 @@ int fftenkf_analyze_dst(const fftenkf_ens* e, const void* data, const void* R_ds
     if (data == nullptr || out == nullptr) return fail(FFTENKF_EINVAL, "data and out are required");
     if (misaligned(data, 16) || misaligned(out, 16) || (R_dst != nullptr && misaligned(R_dst, 16)))
       return fail(FFTENKF_EINVAL, "data, R_dst and out must be 16-byte aligned");
-    if (R_dst == nullptr && !(e->r_scalar >= 0.0)) return fail(FFTENKF_EINVAL, "r_scalar must be >= 0 when R_dst is NULL");
+    if (R_dst == nullptr && (st = check_r_scalar(e->r_scalar, e->dtype, "")) != FFTENKF_OK) return st;
     const size_t s = dsize(e->dtype);
     const size_t field = (size_t)e->ny * e->nx * s;
     const size_t ens_b = field * e->n_members;

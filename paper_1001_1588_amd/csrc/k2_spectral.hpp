@@ -102,19 +102,23 @@ __device__ __forceinline__ void draw_pair(const BinNoise<T>& b, int p, uint32_t 
 }
 
 // Eq. (2) at point i of a thread: the sample variance of the N members'
-// unnormalised coefficients times var_scale = 1 / ((N - 1) n).
+// unnormalised coefficients times var_scale = 1 / ((N - 1) n).  The deviations
+// are formed from s_f = u_f - u_0 (member 0 has s_0 = 0), which leaves them
+// unchanged in exact arithmetic and makes the variance exactly zero when every
+// member is the same, so the gain guard sees a collapsed ensemble as one.
 template <typename T, int NMAX, int P>
 __device__ __forceinline__ T sample_variance(const cx<T> (&u)[NMAX][P], int i, int N, T invN, T var_scale) {
+  const cx<T> u0 = u[0][i];
   cx<T> mean{T(0), T(0)};
 #pragma unroll
-  for (int f = 0; f < NMAX; ++f)
-    if (f < N) mean = mean + u[f][i];
+  for (int f = 1; f < NMAX; ++f)
+    if (f < N) mean = mean + (u[f][i] - u0);
   mean = scale(mean, invN);
-  T var = T(0);
+  T var = mean.re * mean.re + mean.im * mean.im;  // member 0: deviation -mean
 #pragma unroll
-  for (int f = 0; f < NMAX; ++f)
+  for (int f = 1; f < NMAX; ++f)
     if (f < N) {
-      const cx<T> d = u[f][i] - mean;
+      const cx<T> d = (u[f][i] - u0) - mean;
       var += d.re * d.re + d.im * d.im;
     }
   return var * var_scale;
@@ -204,6 +208,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   const T n_tot = T(a.nx) * T(ny);
   const T invN = T(1) / T(N);
   const T var_scale = T(1) / (T(N - 1) * n_tot);  // unitary (eigenvalue) scale
+  const T sqrt_n = sqrt_t<T>(n_tot);
   const T* __restrict__ Rspec = static_cast<const T*>(a.R_spec);
   T gain[P], amp[P];
   int ky[P];
@@ -221,7 +226,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
       if (valid_w) static_cast<T*>(a.chat_map)[(size_t)ky[i] * nh + kx] = chat;
       csum += valid_w ? chat : T(0);
     }
-    amp[i] = sqrt_t<T>(n_tot * rb);
+    amp[i] = sqrt_n * sqrt_t<T>(rb);  // sqrt(n R), without overflow of n R
     if (a.mode == K2_DEBUG_SPECTRA && valid_w) {
       const size_t bin = (size_t)ky[i] * nh + kx;
       static_cast<T*>(a.dbg_chat)[bin] = chat;

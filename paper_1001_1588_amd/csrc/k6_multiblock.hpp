@@ -5,9 +5,8 @@
 // single-block sweep (k2_spectral.hpp).  Per bin, with delta_k = u_hat^(0)_k -
 // mean^(0) the observed block's member deviations:
 //   c_hat^(00) = 1/(N-1) sum_k |delta_k|^2                        (eq. (2))
-//   c_hat^(j0) = 1/(N-1) sum_k u_hat^(j)_k conj(delta_k)          (eq. (7), the
-//                conjugate on the observed factor; sum_k delta_k = 0 removes the
-//                mean of block j)
+//   c_hat^(j0) = 1/(N-1) sum_k (u_hat^(j)_k - mean^(j)) conj(delta_k)   (eq. (7),
+//                the conjugate on the observed factor)
 //   u_hat^(j)a_k = u_hat^(j)_k + c_hat^(j0) / (c_hat^(00) + R) (d_hat + e_hat_k - u_hat^(0)_k)   (eq. (6))
 // with the innovation written d_hat - mean^(0) + e_hat_k - delta_k.  A unit
 // keeps delta (N values per bin) and d_hat - mean^(0) in registers, and streams
@@ -108,6 +107,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
   const T n_tot = T(a.nx) * T(ny);
   const T invN = T(1) / T(N);
   const T var_scale = T(1) / (T(N - 1) * n_tot);  // unitary (eigenvalue) scale
+  const T sqrt_n = sqrt_t<T>(n_tot);
   const T* __restrict__ Rspec = static_cast<const T*>(a.R_spec);
   cx<T> mean0[P];
   T c00[P], den[P], amp[P];
@@ -116,10 +116,16 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     ky[i] = k2 + R * (t2 + TF2 * i);
+    // deviations formed from s_k = u_k - u_0 (exactly zero for a collapsed block)
+    const cx<T> u0 = del[0][i];
     cx<T> mean{T(0), T(0)};
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k)
-      if (k < N) mean = mean + del[k][i];
+    for (int k = 1; k < NMAX; ++k)
+      if (k < N) {
+        del[k][i] = del[k][i] - u0;
+        mean = mean + del[k][i];
+      }
+    del[0][i] = cx<T>{T(0), T(0)};
     mean = scale(mean, invN);
     T var = T(0);
 #pragma unroll
@@ -128,14 +134,14 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
         del[k][i] = del[k][i] - mean;
         var += del[k][i].re * del[k][i].re + del[k][i].im * del[k][i].im;
       }
-    mean0[i] = mean;
-    dm[0][i] = dm[0][i] - mean;
+    mean0[i] = u0 + mean;
+    dm[0][i] = dm[0][i] - mean0[i];
     c00[i] = var * var_scale;
     T rb = T(a.r_scalar);
     if (Rspec != nullptr && g.valid) rb = Rspec[(size_t)ky[i] * nh + kx];
     den[i] = c00[i] + rb;
     none[i] = den[i] < tiny_normal<T>();
-    amp[i] = sqrt_t<T>(n_tot * rb);
+    amp[i] = sqrt_n * sqrt_t<T>(rb);  // sqrt(n R), without overflow of n R
   }
 
   // ---- every block: gain, update with the regenerated perturbations, inverse
@@ -206,10 +212,19 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
     forward(v);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
+      // eq. (7) with both factors centred: block j's members relative to its
+      // member 0, minus their mean (the deviations of block 0 sum to zero only
+      // up to rounding, so block j is not left uncentred)
+      const cx<T> v0 = v[0][i];
+      cx<T> vm{T(0), T(0)};
+#pragma unroll
+      for (int k = 1; k < NMAX; ++k)
+        if (k < N) vm = vm + (v[k][i] - v0);
+      vm = scale(vm, invN);
       cx<T> s{T(0), T(0)};
 #pragma unroll
       for (int k = 0; k < NMAX; ++k)
-        if (k < N) s = s + v[k][i] * conj(del[k][i]);
+        if (k < N) s = s + ((v[k][i] - v0) - vm) * conj(del[k][i]);
       const cx<T> cj = scale(s, var_scale);
       G[i] = none[i] ? cx<T>{T(0), T(0)} : cx<T>{cj.re / den[i], cj.im / den[i]};
     }

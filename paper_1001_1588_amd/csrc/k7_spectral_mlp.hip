@@ -130,6 +130,13 @@ __global__ __launch_bounds__(kThreads, 2) void k7_spectral_mlp(const K7Args a) {
   }
   const float mu = red[0] / (float)total;
   if (blockIdx.x == 0 && tid == 0 && a.mu_out != nullptr) *a.mu_out = mu;
+  // the features divide by mu: where it is not a positive normal number (no
+  // spread anywhere, or an overflow; NaN fails both tests) the estimate falls
+  // back to the plain sample spectrum
+  if (!(mu >= 1.17549435e-38f && mu <= 3.40282347e+38f)) {
+    for (long b = (long)blockIdx.x * kThreads + tid; b < total; b += (long)gridDim.x * kThreads) a.lam[b] = chat[b];
+    return;
+  }
   const float inv_mu = 1.f / mu;
   const float b4 = a.b4[0];
 

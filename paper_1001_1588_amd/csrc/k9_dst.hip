@@ -124,15 +124,17 @@ __global__ __launch_bounds__(256) void dst_quad(const K9Args a) {
       dc[N * plane + bin] = alpha[p] * X[NMAX][p];
       return;
     }
+    // deviations formed from X_f - X_0 (exactly zero for a collapsed ensemble)
+    const T x0 = X[0][p];
     T mean = T(0);
 #pragma unroll
-    for (int f = 0; f < NMAX; ++f)
-      if (f < N) mean += X[f][p];
+    for (int f = 1; f < NMAX; ++f)
+      if (f < N) mean += X[f][p] - x0;
     mean *= invN;
-    T var = T(0);
+    T var = mean * mean;
 #pragma unroll
-    for (int f = 0; f < NMAX; ++f)
-      if (f < N) var += (X[f][p] - mean) * (X[f][p] - mean);
+    for (int f = 1; f < NMAX; ++f)
+      if (f < N) var += ((X[f][p] - x0) - mean) * ((X[f][p] - x0) - mean);
     const T c = alpha[p] * alpha[p] * var * invN1;
     const T r = Rd != nullptr ? Rd[(size_t)s1 * n2 + s2] : T(a.r_scalar);
     const T den = c + r;

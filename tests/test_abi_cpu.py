@@ -217,3 +217,32 @@ def test_dst_validation(built_lib):
     # the sine-basis analysis reorders inside sweeps 1 and 3: same workspace
     for (N, ny, nx, dt) in [(20, 2048, 2048, 0), (5, 64, 64, 1)]:
         assert lib.fftenkf_workspace_bytes_dst(N, ny, nx, dt) == lib.fftenkf_workspace_bytes(N, ny, nx, dt) > 0
+
+
+@pytest.mark.parametrize("r,dtype,status", [
+    (float("inf"), _lib.F32, _lib.EINVAL),
+    (float("inf"), _lib.F64, _lib.EINVAL),
+    (float("-inf"), _lib.F64, _lib.EINVAL),
+    (1e39, _lib.F32, _lib.EINVAL),        # finite in double, infinite in float32
+], ids=lambda v: str(v))
+def test_non_finite_r_scalar_rejected_by_every_entry_point(built_lib, r, dtype, status):
+    """R = r I needs r finite in the working precision: an infinite r gives an
+    infinite perturbation amplitude where the gain is exactly 0 (0 * inf = NaN)."""
+    lib = _lib.lib()
+    e = _ens(r_scalar=r, dtype=dtype, n_members=4, workspace_bytes=1 << 30)
+    assert call(e) == status
+    assert "r_scalar" in lib.fftenkf_last_error().decode()
+    assert lib.fftenkf_analyze_multi(ctypes.byref(e), 2, 0x200000, None, 1, 0x300000) == status
+    assert lib.fftenkf_analyze_dst(ctypes.byref(e), 0x200000, None, 1, 0x300000) == status
+    f = _lib.Filter(ny=16, nx=16, members=0x100000, data=0x200000, R_spec=None, out=0x300000, workspace=0x800000,
+                    workspace_bytes=1 << 20, r_scalar=r, seed=1)
+    assert lib.fftenkf_analyze_batch(4, dtype, (_lib.Filter * 1)(f), 1, None) == status
+    assert "filter 0" in lib.fftenkf_last_error().decode()
+
+
+def test_large_finite_r_scalar_accepted_by_validation(built_lib):
+    """1e39 is finite in float64: validation passes it (the call then fails only
+    because these fake pointers are not device memory)."""
+    e = _ens(r_scalar=1e39, dtype=_lib.F64, workspace_bytes=1 << 30)
+    assert call(e) != _lib.OK
+    assert "r_scalar" not in _lib.lib().fftenkf_last_error().decode()

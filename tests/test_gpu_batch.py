@@ -145,3 +145,44 @@ def test_device_twin_statistics():
     kx = torch.arange(65)[None, :].double()
     high = ((ky ** 2 + kx ** 2) > 40 ** 2).to(DEV)
     assert abs(float(resid[high].mean()) / 0.01 - 1) < 0.05
+
+
+def test_batch_at_the_benchmark_shape():
+    """The batched workload's own law: N = 16, float32, square sides from
+    {64, 128, 256, 512, 1024} (two of each, shuffled), spectrum (1+|k|^2)^-2,
+    R = 0.01 I, tile rows chosen by the autotuner.  Every filter is checked
+    against the oracle (the library FFT form from 512 up, which the oracle's
+    tests pin to its matrix form) and bitwise against a single-filter call, and
+    the captured graph reproduces the eager batch."""
+    from paper_1001_1588_amd import autotune
+
+    sides = [512, 64, 1024, 128, 256, 1024, 64, 512, 256, 128]
+    N = 16
+    tws = [twin.make_twin(s, s, N, seed=900 + i, dtype=np.float32, kind="matern2", r=0.01)
+           for i, s in enumerate(sides)]
+    grids = sorted({(s, s) for s in sides})
+    try:
+        autotune.tune(grids, N, torch.float32, reps=2)
+        ens = [dev(t.ens) for t in tws]
+        data = [dev(t.data) for t in tws]
+        b = _lib.Batch(ens, data, [0.01] * len(sides), [t.seed for t in tws])
+        outs = [o.clone() for o in b.run()]
+        torch.cuda.synchronize()
+        for i, t in enumerate(tws):
+            single = _lib.analyze(ens[i], data[i], 0.01, t.seed)
+            torch.cuda.synchronize()
+            assert torch.equal(outs[i], single), f"filter {i} ({sides[i]}^2) differs from the single-filter analysis"
+            ref = enkf.analyze(t.ens, t.data, 0.01, t.seed, method="matmul" if sides[i] <= 256 else "fft")
+            assert rel_l2(outs[i].cpu().numpy(), ref) <= 1e-5, f"filter {i} ({sides[i]}^2)"
+        b.capture()
+        for rep in range(2):
+            for o in b.out:
+                o.zero_()
+            torch.cuda.synchronize()
+            replay = b.replay()
+            torch.cuda.synchronize()
+            for i in range(len(sides)):
+                assert torch.equal(replay[i], outs[i]), f"replay {rep}, filter {i}"
+    finally:
+        for g in grids:
+            _lib.set_tile_rows(g[0], g[1], torch.float32, 0)
