@@ -107,7 +107,7 @@ size_t dsize(int dtype) { return dtype == FFTENKF_F64 ? 8 : 4; }
 
 // Grid factorisation ny = R * L and the unit shape of the spectral sweep.
 struct Plan {
-  int R, L, P, C, units_main, units_total, group_xcd;
+  int R, L, P, C, Cn, units_main, units_total, group_xcd;
   size_t main_elems, nyq_elems;  // complex elements of the two spectral regions
   size_t off_nyq, off_chat, off_lam, off_part;  // byte offsets in the workspace
   size_t ws_bytes;
@@ -165,8 +165,9 @@ Plan make_plan(int N, int ny, int nx, int dtype) {
   if (c > nxh) c = nxh;
   if (c < 1) c = 1;
   p.C = c;
+  p.Cn = c;
   p.units_main = p.R * (nxh / c);
-  p.units_total = p.units_main + (p.R + c - 1) / c;
+  p.units_total = p.units_main + (p.R + p.Cn - 1) / p.Cn;
   // group the units that share 128-byte lines on one XCD when segments are shorter
   const int seg = c * 2 * (int)dsize(dtype);
   const int g = seg < 128 ? 128 / seg : 1;
@@ -182,6 +183,24 @@ Plan make_plan(int N, int ny, int nx, int dtype) {
   p.off_part = round256(p.off_lam + plane);
   p.ws_bytes = round256(p.off_part + (size_t)p.units_total * sizeof(float));
   return p;
+}
+
+// The spectral sweep's share of K2Args: the plan's geometry and the byte sizes
+// of the two workspace regions (addressed with 32-bit offsets).
+void set_k2_geometry(K2Args& a, const Plan& p, int N, int ny, int nx, int dtype) {
+  const size_t cplx = 2 * dsize(dtype);
+  a.N = N;
+  a.ny = ny;
+  a.nx = nx;
+  a.R = p.R;
+  a.L = p.L;
+  a.C = p.C;
+  a.Cn = p.Cn;
+  a.units_main = p.units_main;
+  a.units_total = p.units_total;
+  a.group_xcd = p.group_xcd;
+  a.main_bytes = (uint32_t)(p.main_elems * cplx);
+  a.nyq_bytes = (uint32_t)(p.nyq_elems * cplx);
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -212,6 +231,9 @@ int validate_shape(const fftenkf_ens* e, Plan* plan) {
   if (k2_member_bucket(e->dtype, e->n_members) == 0)
     return fail(FFTENKF_EUNSUPPORTED, "n_members = %d exceeds %d for this dtype", e->n_members, fftenkf_max_members(e->dtype));
   *plan = make_plan(e->n_members, e->ny, e->nx, e->dtype);
+  if (plan->main_elems * 2 * dsize(e->dtype) >= ((size_t)1 << 31))
+    return fail(FFTENKF_EUNSUPPORTED, "the spectra of %d fields on a %d x %d grid exceed 2 GiB", e->n_members + 1,
+                e->ny, e->nx);
   if (e->members == nullptr) return fail(FFTENKF_EINVAL, "members is NULL");
   if (e->workspace == nullptr) return fail(FFTENKF_EINVAL, "workspace is NULL");
   if (e->workspace_bytes < plan->ws_bytes)
@@ -302,15 +324,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   a2.ws_nyq = ws_nyq;
   a2.R_spec = R_spec;
   a2.r_scalar = e->r_scalar;
-  a2.N = e->n_members;
-  a2.ny = e->ny;
-  a2.nx = e->nx;
-  a2.R = plan.R;
-  a2.L = plan.L;
-  a2.C = plan.C;
-  a2.units_main = plan.units_main;
-  a2.units_total = plan.units_total;
-  a2.group_xcd = plan.group_xcd;
+  set_k2_geometry(a2, plan, e->n_members, e->ny, e->nx, e->dtype);
   a2.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
   a2.key1 = (uint32_t)(seed >> 32);
   a2.mode = mode;
@@ -414,15 +428,7 @@ int run_fft2(const fftenkf_ens* e, const Plan& plan, int inverse, const void* sp
   a2.ws_main = ws_main;
   a2.ws_nyq = ws_nyq;
   a2.r_scalar = 1.0;
-  a2.N = e->n_members;
-  a2.ny = e->ny;
-  a2.nx = e->nx;
-  a2.R = plan.R;
-  a2.L = plan.L;
-  a2.C = plan.C;
-  a2.units_main = plan.units_main;
-  a2.units_total = plan.units_total;
-  a2.group_xcd = plan.group_xcd;
+  set_k2_geometry(a2, plan, e->n_members, e->ny, e->nx, e->dtype);
   a2.chat_map = ws + plan.off_chat;
   a2.partials = ws + plan.off_part;
   a2.tab = tab;
@@ -595,15 +601,7 @@ int run_batch(int N, int dtype, const fftenkf_filter* fs, int n, const std::vect
       b.L = plan.L;
       b.tab = tab;
       K2Args& a2 = b.k2;
-      a2.N = N;
-      a2.ny = b.ny;
-      a2.nx = b.nx;
-      a2.R = plan.R;
-      a2.L = plan.L;
-      a2.C = plan.C;
-      a2.units_main = plan.units_main;
-      a2.units_total = plan.units_total;
-      a2.group_xcd = plan.group_xcd;
+      set_k2_geometry(a2, plan, N, b.ny, b.nx, dtype);
       a2.mode = K2_ANALYZE;
       a2.tab = tab;
       for (int k = 0; k < b.count; ++k) {
@@ -660,15 +658,7 @@ int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void
   a2.ws_main = ws_main;
   a2.ws_nyq = ws_nyq;
   a2.r_scalar = 1.0;
-  a2.N = N;
-  a2.ny = ny;
-  a2.nx = nx;
-  a2.R = plan.R;
-  a2.L = plan.L;
-  a2.C = plan.C;
-  a2.units_main = plan.units_main;
-  a2.units_total = plan.units_total;
-  a2.group_xcd = plan.group_xcd;
+  set_k2_geometry(a2, plan, N, ny, nx, e->dtype);
   a2.chat_map = ws + plan.off_chat;
   a2.partials = ws + plan.off_part;
   a2.tab = tab;

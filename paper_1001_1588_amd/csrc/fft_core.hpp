@@ -56,6 +56,10 @@ template <typename T> __host__ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) 
 // a * (+i)
 template <typename T> __host__ __device__ __forceinline__ cx<T> mul_pi(cx<T> a) { return {-a.im, a.re}; }
 
+// a * b + c with one rounding
+__host__ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T> __host__ __device__ __forceinline__ cx<T> from2(V2<T> v) { return {v.x, v.y}; }
 template <typename T> __host__ __device__ __forceinline__ V2<T> to2(cx<T> a) {
   V2<T> v;
@@ -396,6 +400,34 @@ __device__ __forceinline__ V ld_off(const V* base, uint32_t byte_off) {
 template <typename V>
 __device__ __forceinline__ void st_off(V* base, uint32_t byte_off, V v) {
   *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// Raw buffer access: a resource over [base, base + bytes) (bytes < 2^32), with
+// a per-thread 32-bit offset and a uniform 32-bit offset per access that the
+// hardware adds; an access beyond `bytes` reads zero and writes nothing.  The
+// per-thread offsets of a unit are computed once and reused for every field,
+// whose offset travels in a scalar register, so no 64-bit vector address is
+// formed per access.
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+};
+__device__ __forceinline__ Buf make_buf(const void* base, uint32_t bytes) {
+  return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000)};
+}
+typedef unsigned int u32v2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32v4 __attribute__((ext_vector_type(4)));
+template <typename T> __device__ __forceinline__ V2<T> buf_ld(const Buf& b, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float2 buf_ld<float>(const Buf& b, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ double2 buf_ld<double>(const Buf& b, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_st(const Buf& b, uint32_t voff, uint32_t soff, float2 v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32v2, v), b.r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st(const Buf& b, uint32_t voff, uint32_t soff, double2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32v4, v), b.r, (int)voff, (int)soff, 0);
 }
 
 // Loads of data read once: the nontemporal hint lets the caches stream them

@@ -88,19 +88,6 @@ __device__ __forceinline__ BinNoise<T> bin_noise(int kx, int ky, int nxh, int ny
   return b;
 }
 
-// e_hat of members 2p and 2p + 1 at one bin, amp = sqrt(n R) (the unnormalised
-// spectrum's scale): one Philox call, counter (ctr0, p, 0, 0), two Box-Muller pairs.
-template <typename T>
-__device__ __forceinline__ void draw_pair(const BinNoise<T>& b, int p, uint32_t key0, uint32_t key1, T amp,
-                                          cx<T>& e0, cx<T>& e1) {
-  const u32x4 w = philox4x32_10(u32x4{b.ctr0, (uint32_t)p, 0u, 0u}, key0, key1);
-  T za, zb;
-  box_muller<T>(w.x0, w.x1, za, zb);
-  e0 = cx<T>{amp * b.zs * za, amp * b.zi * zb};
-  box_muller<T>(w.x2, w.x3, za, zb);
-  e1 = cx<T>{amp * b.zs * za, amp * b.zi * zb};
-}
-
 // Eq. (2) at point i of a thread: the sample variance of the N members'
 // unnormalised coefficients times var_scale = 1 / ((N - 1) n).  The deviations
 // are formed from s_f = u_f - u_0 (member 0 has s_0 = 0), which leaves them
@@ -124,9 +111,8 @@ __device__ __forceinline__ T sample_variance(const cx<T> (&u)[NMAX][P], int i, i
   return var * var_scale;
 }
 
-// SPLIT compiles the modes that stop or start at the transformed fields
-// (K2_STATS, K2_CHAT, K2_INVERSE); the single-pass modes are compiled without
-// them.
+// SPLIT compiles every mode but K2_ANALYZE (the statistics-only, inverse-only
+// and test-export modes); the single-pass variant is compiled without them.
 // The work of one block; `unit` is its index within one analysis.
 template <typename T, int L, int NMAX, bool SPLIT>
 __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
@@ -145,18 +131,20 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   const int t2 = tid / C;
   const int N = a.N, R = a.R, ny = a.ny;
   const int nxh = a.nx >> 1, nh = nxh + 1;
+  const int mode = SPLIT ? a.mode : K2_ANALYZE;
 
-  // unit geometry: a uniform base pointer, a uniform field stride and per-thread
-  // 32-bit byte offsets of the P elements
-  const SpectralUnit<T> g = spectral_unit<T>(a.ws_main, a.ws_nyq, unit, c, C, R, L, ny, nxh, a.units_main,
+  // unit geometry; every field is read and written through one buffer
+  // resource over the unit's region, with per-thread byte offsets of the P
+  // elements (shared by all fields) and a uniform byte offset per field
+  const SpectralUnit<T> g = spectral_unit<T>(a.ws_main, a.ws_nyq, unit, c, C, a.Cn, R, L, ny, nxh, a.units_main,
                                              a.units_total, a.group_xcd);
-  const int k2 = g.k2, kx = g.kx, cc = g.cc;
+  const int k2 = g.k2, kx = g.kx;
   const bool valid = g.valid;
-  V2<T>* const ubase = g.ubase;
-  const uint32_t fstride = g.fstride, sy = g.sy;
+  const Buf buf = make_buf(g.nyq ? a.ws_nyq : a.ws_main, g.nyq ? a.nyq_bytes : a.main_bytes);
+  const uint32_t fbytes = g.fstride * (uint32_t)sizeof(V2<T>);
   uint32_t voff[P];
 #pragma unroll
-  for (int i = 0; i < P; ++i) voff[i] = ((uint32_t)(t2 + TF2 * i) * sy + (uint32_t)cc) * (uint32_t)sizeof(V2<T>);
+  for (int i = 0; i < P; ++i) voff[i] = g.cbytes + (uint32_t)(t2 + TF2 * i) * g.sy * (uint32_t)sizeof(V2<T>);
   V2<T>* lds0 = reinterpret_cast<V2<T>*>(k2_lds_raw);
   LdsPair lp{lds0, lds0 + FB * SEQP, 0, c};
   // the twiddles (visible to all threads after the first exchange's barrier)
@@ -168,138 +156,156 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   static_for<0, NMAX>([&](auto F) {
     constexpr int f = decltype(F)::value;
     if (f < N) {
-      const V2<T>* fb = ubase + (size_t)f * fstride;
 #pragma unroll
-      for (int i = 0; i < P; ++i) u[f][i] = from2<T>(ld_off(fb, voff[i]));
+      for (int i = 0; i < P; ++i) u[f][i] = from2<T>(buf_ld<T>(buf, voff[i], (uint32_t)f * fbytes));
     } else {
 #pragma unroll
       for (int i = 0; i < P; ++i) u[f][i] = cx<T>{T(0), T(0)};
     }
   });
-  {
-    const V2<T>* fb = ubase + (size_t)N * fstride;
 #pragma unroll
-    for (int i = 0; i < P; ++i) dv[0][i] = from2<T>(ld_off(fb, voff[i]));
-  }
+  for (int i = 0; i < P; ++i) dv[0][i] = from2<T>(buf_ld<T>(buf, voff[i], (uint32_t)N * fbytes));
 
   // forward length-L transforms (the inverse-only mode starts from transformed fields)
-  const bool transformed = SPLIT && a.mode == K2_INVERSE;
-  if (!transformed) {
+  if (mode != K2_INVERSE) {
 #pragma unroll
-  for (int f0 = 0; f0 < NMAX; f0 += FB) {
-    if (f0 < N) {
-      cx<T> blk[FB][P];
+    for (int f0 = 0; f0 < NMAX; f0 += FB) {
+      if (f0 < N) {
+        cx<T> blk[FB][P];
 #pragma unroll
-      for (int b = 0; b < FB; ++b)
+        for (int b = 0; b < FB; ++b)
 #pragma unroll
-        for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
-      fft_forward<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+          for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
+        fft_forward<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
 #pragma unroll
-      for (int b = 0; b < FB; ++b)
+        for (int b = 0; b < FB; ++b)
 #pragma unroll
-        for (int i = 0; i < P; ++i) u[f0 + b][i] = blk[b][i];
+          for (int i = 0; i < P; ++i) u[f0 + b][i] = blk[b][i];
+      }
     }
+    fft_forward<T, L, P, 1, SEQP, false, Lay, L>(dv, t2, lp, C, tw);
   }
-  fft_forward<T, L, P, 1, SEQP, false, Lay, L>(dv, t2, lp, C, tw);
-  }
-  const bool valid_w = valid;
 
-  // ---- eq. (2) per bin, then the gain of eq. (3)
+  // ---- eq. (2) per bin, then the gain g of eq. (3).  The update of a member
+  // at a bin, u + g (d + e - u) with e = sqrt(n R) (zs rho cos, zi rho sin), is
+  // evaluated as u (1 - g) + g d + rho (g sqrt(n R) zs cos, g sqrt(n R) zi sin):
+  // the bin's factors omg = 1 - g, gd = g d and ga_re, ga_im are formed once.
   const T n_tot = T(a.nx) * T(ny);
   const T invN = T(1) / T(N);
   const T var_scale = T(1) / (T(N - 1) * n_tot);  // unitary (eigenvalue) scale
   const T sqrt_n = sqrt_t<T>(n_tot);
   const T* __restrict__ Rspec = static_cast<const T*>(a.R_spec);
-  T gain[P], amp[P];
+  T gain[P], amp_re[P], amp_im[P], omg[P], ga_re[P], ga_im[P];
+  cx<T> gd[P];
+  uint32_t ctr0[P];
   int ky[P];
   T csum = T(0);
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     ky[i] = k2 + R * (t2 + TF2 * i);
     T chat = sample_variance<T, NMAX, P>(u, i, N, invN, var_scale);
-    if (a.lam_map != nullptr && valid_w) chat = static_cast<const T*>(a.lam_map)[(size_t)ky[i] * nh + kx];
+    if (a.lam_map != nullptr && valid) chat = static_cast<const T*>(a.lam_map)[(size_t)ky[i] * nh + kx];
     T rb = T(a.r_scalar);
-    if (Rspec != nullptr && valid_w) rb = Rspec[(size_t)ky[i] * nh + kx];
+    if (Rspec != nullptr && valid) rb = Rspec[(size_t)ky[i] * nh + kx];
     const T den = chat + rb;
     gain[i] = den < tiny_normal<T>() ? T(0) : chat / den;
-    if (SPLIT && (a.mode == K2_STATS || a.mode == K2_CHAT)) {
-      if (valid_w) static_cast<T*>(a.chat_map)[(size_t)ky[i] * nh + kx] = chat;
-      csum += valid_w ? chat : T(0);
-    }
-    amp[i] = sqrt_n * sqrt_t<T>(rb);  // sqrt(n R), without overflow of n R
-    if (a.mode == K2_DEBUG_SPECTRA && valid_w) {
-      const size_t bin = (size_t)ky[i] * nh + kx;
-      static_cast<T*>(a.dbg_chat)[bin] = chat;
-      static_cast<T*>(a.dbg_gain)[bin] = gain[i];
-      if (a.dbg_spec != nullptr) {
-        V2<T>* sp = static_cast<V2<T>*>(a.dbg_spec);
-        const T us = T(1) / sqrt_t<T>(n_tot);
-        const size_t plane = (size_t)ny * nh;
+    const BinNoise<T> bn = bin_noise<T>(kx, ky[i], nxh, ny);
+    const T amp = sqrt_n * sqrt_t<T>(rb);  // sqrt(n R), without overflow of n R
+    amp_re[i] = amp * bn.zs;
+    amp_im[i] = amp * bn.zi;
+    ctr0[i] = bn.ctr0;
+    omg[i] = T(1) - gain[i];
+    gd[i] = scale(dv[0][i], gain[i]);
+    ga_re[i] = gain[i] * amp_re[i];
+    ga_im[i] = gain[i] * amp_im[i];
+    if constexpr (SPLIT) {
+      if (mode == K2_STATS || mode == K2_CHAT) {
+        if (valid) static_cast<T*>(a.chat_map)[(size_t)ky[i] * nh + kx] = chat;
+        csum += valid ? chat : T(0);
+      }
+      if (mode == K2_DEBUG_SPECTRA && valid) {
+        const size_t bin = (size_t)ky[i] * nh + kx;
+        static_cast<T*>(a.dbg_chat)[bin] = chat;
+        static_cast<T*>(a.dbg_gain)[bin] = gain[i];
+        if (a.dbg_spec != nullptr) {
+          V2<T>* sp = static_cast<V2<T>*>(a.dbg_spec);
+          const T us = T(1) / sqrt_n;
+          const size_t plane = (size_t)ny * nh;
 #pragma unroll
-        for (int f = 0; f < NMAX; ++f)
-          if (f < N) sp[f * plane + bin] = to2<T>(scale(u[f][i], us));
-        sp[N * plane + bin] = to2<T>(scale(dv[0][i], us));
+          for (int f = 0; f < NMAX; ++f)
+            if (f < N) sp[f * plane + bin] = to2<T>(scale(u[f][i], us));
+          sp[N * plane + bin] = to2<T>(scale(dv[0][i], us));
+        }
       }
     }
   }
-  if (a.mode == K2_DEBUG_SPECTRA) return;  // no synchronisation follows
-  if (SPLIT && (a.mode == K2_STATS || a.mode == K2_CHAT)) {
-    // transformed fields back in place (K2_STATS), and this block's sum of c_hat
-    if (valid && a.mode == K2_STATS) {
+  if constexpr (SPLIT) {
+    if (mode == K2_DEBUG_SPECTRA) return;  // no synchronisation follows
+    if (mode == K2_STATS || mode == K2_CHAT) {
+      // transformed fields back in place (K2_STATS), and this block's sum of c_hat
+      if (valid && mode == K2_STATS) {
 #pragma unroll
-      for (int f = 0; f < NMAX; ++f)
-        if (f < N) {
-          V2<T>* fb = ubase + (size_t)f * fstride;
+        for (int f = 0; f < NMAX; ++f)
+          if (f < N) {
 #pragma unroll
-          for (int i = 0; i < P; ++i) st_off(fb, voff[i], to2<T>(u[f][i]));
-        }
-      V2<T>* fb = ubase + (size_t)N * fstride;
+            for (int i = 0; i < P; ++i) buf_st(buf, voff[i], (uint32_t)f * fbytes, to2<T>(u[f][i]));
+          }
 #pragma unroll
-      for (int i = 0; i < P; ++i) st_off(fb, voff[i], to2<T>(dv[0][i]));
+        for (int i = 0; i < P; ++i) buf_st(buf, voff[i], (uint32_t)N * fbytes, to2<T>(dv[0][i]));
+      }
+      T* red = reinterpret_cast<T*>(k2_lds_raw);
+      __syncthreads();  // the exchange buffers are free again
+      red[tid] = csum;
+      __syncthreads();
+      if (tid == 0) {
+        T tot = T(0);
+        for (int k = 0; k < (int)blockDim.x; ++k) tot += red[k];
+        static_cast<float*>(a.partials)[unit] = (float)tot;
+      }
+      return;
     }
-    T* red = reinterpret_cast<T*>(k2_lds_raw);
-    __syncthreads();  // the exchange buffers are free again
-    red[tid] = csum;
-    __syncthreads();
-    if (tid == 0) {
-      T tot = T(0);
-      for (int k = 0; k < (int)blockDim.x; ++k) tot += red[k];
-      static_cast<float*>(a.partials)[unit] = (float)tot;
-    }
-    return;
   }
 
-  // ---- perturbations and update, two members per Philox call: the pairs
-  // [PB, PE) of every bin the thread holds
+  // ---- perturbations and update, two members per Philox call (counter
+  // (bin, p, 0, 0) gives members 2p and 2p + 1): the pairs [PB, PE) of every
+  // bin the thread holds
   auto perturb = [&](auto PB, auto PE) __attribute__((always_inline)) {
     static_for<0, P>([&](auto I) __attribute__((always_inline)) {
       constexpr int i = decltype(I)::value;
-      const BinNoise<T> bn = bin_noise<T>(kx, ky[i], nxh, ny);
       static_for<decltype(PB)::value, decltype(PE)::value>([&](auto PP) __attribute__((always_inline)) {
         constexpr int p = decltype(PP)::value;
         if (2 * p < N) {
-          cx<T> e0, e1;
-          draw_pair<T>(bn, p, a.key0, a.key1, amp[i], e0, e1);
-          if (a.mode == K2_DEBUG_PERTURB) {  // test export of e_hat (unitary scale)
-            if (valid_w) {
+          const u32x4 w = philox4x32_10(u32x4{ctr0[i], (uint32_t)p, 0u, 0u}, a.key0, a.key1);
+          T rho0, c0, s0, rho1, c1, s1;
+          box_muller_parts<T>(w.x0, w.x1, rho0, c0, s0);
+          box_muller_parts<T>(w.x2, w.x3, rho1, c1, s1);
+          if (SPLIT && mode == K2_DEBUG_PERTURB) {  // test export of e_hat (unitary scale)
+            if (valid) {
+              const cx<T> e0{amp_re[i] * (rho0 * c0), amp_im[i] * (rho0 * s0)};
+              const cx<T> e1{amp_re[i] * (rho1 * c1), amp_im[i] * (rho1 * s1)};
               V2<T>* ep = static_cast<V2<T>*>(a.dbg_e);
-              const T us = T(1) / sqrt_t<T>(n_tot);
+              const T us = T(1) / sqrt_n;
               const size_t bin = (size_t)ky[i] * nh + kx, plane = (size_t)ny * nh;
               ep[(2 * p) * plane + bin] = to2<T>(scale(e0, us));
               if (2 * p + 1 < N) ep[(2 * p + 1) * plane + bin] = to2<T>(scale(e1, us));
             }
           } else {
             const cx<T> ua = u[2 * p][i], ub = u[2 * p + 1][i];
-            u[2 * p][i] = ua + scale(dv[0][i] + e0 - ua, gain[i]);
-            if (2 * p + 1 < N) u[2 * p + 1][i] = ub + scale(dv[0][i] + e1 - ub, gain[i]);
+            u[2 * p][i] = cx<T>{fma_t(rho0 * ga_re[i], c0, fma_t(ua.re, omg[i], gd[i].re)),
+                                fma_t(rho0 * ga_im[i], s0, fma_t(ua.im, omg[i], gd[i].im))};
+            if (2 * p + 1 < N)
+              u[2 * p + 1][i] = cx<T>{fma_t(rho1 * ga_re[i], c1, fma_t(ub.re, omg[i], gd[i].re)),
+                                      fma_t(rho1 * ga_im[i], s1, fma_t(ub.im, omg[i], gd[i].im))};
           }
         }
       });
     });
   };
-  if (a.mode == K2_DEBUG_PERTURB) {
-    perturb(std::integral_constant<int, 0>{}, std::integral_constant<int, NMAX / 2>{});
-    return;  // no synchronisation follows
+  if constexpr (SPLIT) {
+    if (mode == K2_DEBUG_PERTURB) {
+      perturb(std::integral_constant<int, 0>{}, std::integral_constant<int, NMAX / 2>{});
+      return;  // no synchronisation follows
+    }
   }
 
   // ---- per LDS round: update its members (their perturbations are drawn here,
@@ -308,7 +314,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   static_for<0, NMAX, FB>([&](auto F0) __attribute__((always_inline)) {
     constexpr int f0 = decltype(F0)::value;
     if (f0 < N) {
-      if (!(SPLIT && a.mode == K2_INVERSE))
+      if (mode != K2_INVERSE)
         perturb(std::integral_constant<int, f0 / 2>{}, std::integral_constant<int, (f0 + FB) / 2>{});
       cx<T> blk[FB][P];
 #pragma unroll
@@ -320,9 +326,8 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
 #pragma unroll
         for (int b = 0; b < FB; ++b)
           if (f0 + b < N) {
-            V2<T>* fb = ubase + (size_t)(f0 + b) * fstride;
 #pragma unroll
-            for (int i = 0; i < P; ++i) st_off(fb, voff[i], to2<T>(blk[b][i]));
+            for (int i = 0; i < P; ++i) buf_st(buf, voff[i], (uint32_t)(f0 + b) * fbytes, to2<T>(blk[b][i]));
           }
       }
     }
@@ -375,8 +380,7 @@ hipError_t launch_k2_variant(const K2Args& a, hipStream_t st) {
 
 template <typename T, int L, int NMAX>
 hipError_t launch_k2_shape(const K2Args& a, hipStream_t st) {
-  const bool split = a.mode == K2_STATS || a.mode == K2_CHAT || a.mode == K2_INVERSE;
-  if (split) return launch_k2_variant<T, L, NMAX, true>(a, st);
+  if (a.mode != K2_ANALYZE) return launch_k2_variant<T, L, NMAX, true>(a, st);
   return launch_k2_variant<T, L, NMAX, false>(a, st);
 }
 

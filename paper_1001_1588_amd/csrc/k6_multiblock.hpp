@@ -47,7 +47,7 @@ __global__ __launch_bounds__(k2_threads_target, (k6_waves<T, NMAX>())) void k6_m
   const int t2 = tid / C;
   const int N = a.N, M = a.M, R = a.R, ny = a.ny;
   const int nxh = a.nx >> 1, nh = nxh + 1;
-  const SpectralUnit<T> g = spectral_unit<T>(a.ws_main, a.ws_nyq, blockIdx.x, c, C, R, L, ny, nxh, a.units_main,
+  const SpectralUnit<T> g = spectral_unit<T>(a.ws_main, a.ws_nyq, blockIdx.x, c, C, C, R, L, ny, nxh, a.units_main,
                                              a.units_total, a.group_xcd);
   const int k2 = g.k2, kx = g.kx;
   uint32_t voff[P];

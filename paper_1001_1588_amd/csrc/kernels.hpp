@@ -40,6 +40,8 @@ struct K1Args {
 //   eigenvalues are read from it (an estimate, or a prescribed spectrum).
 // K2_INVERSE: starts from transformed fields and only applies the inverse
 //   length-L transforms (the c2r test export).
+// Only K2_ANALYZE runs in the single-pass kernel variant; every other mode is
+// compiled into a separate variant, so the analysis kernel carries none of their code.
 enum K2Mode {
   K2_ANALYZE = 0,
   K2_DEBUG_SPECTRA = 1,
@@ -52,9 +54,10 @@ enum K2Mode {
 struct K2Args {
   void* ws_main;
   void* ws_nyq;
+  uint32_t main_bytes, nyq_bytes;  // sizes of the two regions (each below 2^31)
   const void* R_spec;  // [ny][nx/2+1] or nullptr
   double r_scalar;
-  int N, ny, nx, R, L, C, units_main, units_total;
+  int N, ny, nx, R, L, C, Cn, units_main, units_total;  // Cn: k2 columns of a Nyquist unit
   int group_xcd;  // G > 1: blocks b, b+8, .., b+8(G-1) take G adjacent kx chunks of one k2
   uint32_t key0, key1;
   int mode;

@@ -39,6 +39,18 @@ template <typename T>
 __device__ __forceinline__ T uniform_open(uint32_t w) {
   return T((int)(((w >> 9) << 1) | 1u)) * T(5.9604644775390625e-08);
 }
+// The same value in binary32 with one fewer instruction: the float with
+// exponent 0 and mantissa w >> 9 is 1 + (w >> 9) 2^-23, and subtracting
+// 1 - 2^-24 from it is exact (the operands are within a factor of two), which
+// leaves (w >> 9) 2^-23 + 2^-24.
+template <>
+__device__ __forceinline__ float uniform_open<float>(uint32_t w) {
+  return __builtin_bit_cast(float, (w >> 9) | 0x3F800000u) - 0.999999940395355224609375f;
+}
+
+// Box-Muller in parts: rho = sqrt(-2 ln u1), and cos, sin of 2 pi u2; the two
+// standard normals are rho cos and rho sin.
+template <typename T> __device__ __forceinline__ void box_muller_parts(uint32_t wa, uint32_t wb, T& rho, T& c, T& s);
 
 // Two standard normals from two words (Box-Muller): rho (cos 2 pi u2, sin 2 pi u2).
 template <typename T> __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T& a, T& b);
@@ -47,21 +59,27 @@ template <typename T> __device__ __forceinline__ void box_muller(uint32_t wa, ui
 // v_sqrt_f32, v_sin_f32 and v_cos_f32 take their argument in revolutions);
 // u1 >= 2^-24 keeps the logarithm finite and u2 < 1 stays in the hardware range.
 template <>
-__device__ __forceinline__ void box_muller<float>(uint32_t wa, uint32_t wb, float& a, float& b) {
+__device__ __forceinline__ void box_muller_parts<float>(uint32_t wa, uint32_t wb, float& rho, float& c, float& s) {
   const float u1 = uniform_open<float>(wa);
   const float u2 = uniform_open<float>(wb);
-  const float rho = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u1));  // -2 ln 2 log2(u1)
-  a = rho * __builtin_amdgcn_cosf(u2);
-  b = rho * __builtin_amdgcn_sinf(u2);
+  rho = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u1));  // -2 ln 2 log2(u1)
+  c = __builtin_amdgcn_cosf(u2);
+  s = __builtin_amdgcn_sinf(u2);
 }
 
 template <>
-__device__ __forceinline__ void box_muller<double>(uint32_t wa, uint32_t wb, double& a, double& b) {
+__device__ __forceinline__ void box_muller_parts<double>(uint32_t wa, uint32_t wb, double& rho, double& c,
+                                                         double& s) {
   const double u1 = uniform_open<double>(wa);
   const double u2 = uniform_open<double>(wb);
-  const double rho = sqrt(-2.0 * log(u1));
-  double s, c;
+  rho = sqrt(-2.0 * log(u1));
   sincospi(2.0 * u2, &s, &c);
+}
+
+template <typename T>
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, T& a, T& b) {
+  T rho, c, s;
+  box_muller_parts<T>(wa, wb, rho, c, s);
   a = rho * c;
   b = rho * s;
 }

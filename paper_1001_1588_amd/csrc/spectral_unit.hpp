@@ -17,19 +17,22 @@ namespace fftenkf {
 template <typename T>
 struct SpectralUnit {
   int k2, kx;         // this thread's column: frequency k2 of the radix-R stage and kx
-  bool valid;         // false for padding threads of the last Nyquist unit
+  bool valid;         // false for padding threads of a Nyquist unit
+  bool nyq;           // a Nyquist unit (its fields live in ws_nyq)
   V2<T>* ubase;       // uniform base of field 0 of this unit
   uint32_t fstride;   // elements between fields
   uint32_t sy;        // elements between consecutive y1 (or k1)
   int cc;             // this thread's column offset from ubase (0 if not valid)
+  uint32_t cbytes;    // byte offset of this thread's column of field 0 from the start of its region
 };
 
-// Thread column c < C of block `unit`; invalid Nyquist columns read column 0
-// and never write.
+// Thread column c < C of block `unit`.  Nyquist units cover Cn <= C adjacent k2
+// (threads with c >= Cn, and those beyond R, are padding: they read column 0
+// and never write).
 template <typename T>
-__device__ __forceinline__ SpectralUnit<T> spectral_unit(void* ws_main, void* ws_nyq, int unit, int c, int C, int R,
-                                                         int L, int ny, int nxh, int units_main, int units_total,
-                                                         int group_xcd) {
+__device__ __forceinline__ SpectralUnit<T> spectral_unit(void* ws_main, void* ws_nyq, int unit, int c, int C, int Cn,
+                                                         int R, int L, int ny, int nxh, int units_main,
+                                                         int units_total, int group_xcd) {
   SpectralUnit<T> g;
   const int units_nyq = units_total - units_main;
   if (unit >= units_nyq) {
@@ -44,19 +47,24 @@ __device__ __forceinline__ SpectralUnit<T> spectral_unit(void* ws_main, void* ws
     const int kxc = um - g.k2 * nchunk;
     g.kx = kxc * C + c;
     g.valid = true;
-    g.ubase = static_cast<V2<T>*>(ws_main) + (size_t)g.k2 * L * nxh + (size_t)kxc * C;
+    g.nyq = false;
+    const size_t off = (size_t)g.k2 * L * nxh + (size_t)kxc * C;
+    g.ubase = static_cast<V2<T>*>(ws_main) + off;
     g.fstride = (uint32_t)ny * (uint32_t)nxh;
     g.sy = (uint32_t)nxh;
     g.cc = c;
+    g.cbytes = (uint32_t)((off + (size_t)c) * sizeof(V2<T>));
   } else {
     const int v = unit;
-    g.k2 = v * C + c;
+    g.k2 = v * Cn + c;
     g.kx = nxh;
-    g.valid = g.k2 < R;
-    g.ubase = static_cast<V2<T>*>(ws_nyq) + (size_t)v * C;
+    g.valid = c < Cn && g.k2 < R;
+    g.nyq = true;
+    g.ubase = static_cast<V2<T>*>(ws_nyq) + (size_t)v * Cn;
     g.fstride = (uint32_t)ny;
     g.sy = (uint32_t)R;
     g.cc = g.valid ? c : 0;
+    g.cbytes = (uint32_t)(((size_t)v * Cn + (size_t)g.cc) * sizeof(V2<T>));
   }
   return g;
 }
