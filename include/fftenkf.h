@@ -95,6 +95,28 @@ typedef struct fftenkf_ens {
  */
 int fftenkf_analyze(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed, void* out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the analysis
+ * of fftenkf_analyze with the same arguments, except that ens->workspace and
+ * ens->workspace_bytes are ignored.  The workspace is instead a static device
+ * array of fftenkf_noalloc_max_bytes() bytes (64 MiB) that the library holds on
+ * every device it runs on until the process ends; its address on a device is
+ * looked up on the first call there (with that device current).  Shapes whose
+ * fftenkf_workspace_bytes exceeds that size (e.g. more than 13 members on a
+ * 1024 x 1024 grid in float32) return FFTENKF_EINVAL without enqueuing
+ * anything.  No call allocates: nothing in the array needs to start at zero
+ * (sweep 1 writes every element the later sweeps read).  All calls on one GPU
+ * share the array, which keeps the last call's contents: two calls that may
+ * overlap in time on one GPU (different streams, or different host threads
+ * without ordering) race and give undefined results; order them on one stream.
+ * Same kernels, so the output is bitwise that of fftenkf_analyze.
+ */
+int fftenkf_analyze_noalloc(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed, void* out);
+
+/* Size in bytes of the static scratch array of fftenkf_analyze_noalloc. */
+size_t fftenkf_noalloc_max_bytes(void);
+
 /* Bytes of workspace fftenkf_analyze and fftenkf_analyze_learned need: (N+1)
  * spectra of ny*(nx/2+1) complex values, two ny*(nx/2+1) real planes and one
  * float per unit of the spectral sweep, rounded up to 256; 0 if the shape is invalid. */

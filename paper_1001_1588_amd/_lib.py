@@ -66,6 +66,9 @@ _lib: Optional[ctypes.CDLL] = None
 EXPORTS = {
     "fftenkf_analyze": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
     "fftenkf_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "fftenkf_analyze_noalloc": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                               ctypes.c_void_p]),
+    "fftenkf_noalloc_max_bytes": (ctypes.c_size_t, []),
     "fftenkf_max_members": (ctypes.c_int, [ctypes.c_int]),
     "fftenkf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fftenkf_last_error": (ctypes.c_char_p, []),
@@ -179,6 +182,22 @@ def analyze(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, f
     st = lib().fftenkf_analyze(ctypes.byref(e), data.data_ptr(), _ptr(R_t), ctypes.c_uint64(seed & (2**64 - 1)),
                                out.data_ptr())
     _check(st, "fftenkf_analyze")
+    return out
+
+
+def analyze_noalloc(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Tensor, float], seed: int,
+                    out: torch.Tensor) -> torch.Tensor:
+    """fftenkf_analyze_noalloc: the analysis with the library's static scratch as
+    its workspace; `out` must be given (the call allocates nothing)."""
+    if ens.dim() != 3 or not ens.is_cuda or not ens.is_contiguous():
+        raise ValueError("ens must be a contiguous device tensor [N, ny, nx]")
+    N, ny, nx = ens.shape
+    R_t, r = _rspec(R_spec)
+    e = Ens(n_members=N, ny=ny, nx=nx, dtype=_dtype_code(ens), members=ens.data_ptr(), workspace=None,
+            workspace_bytes=0, stream=torch.cuda.current_stream(ens.device).cuda_stream, r_scalar=float(r))
+    st = lib().fftenkf_analyze_noalloc(ctypes.byref(e), data.data_ptr(), _ptr(R_t),
+                                       ctypes.c_uint64(seed & (2**64 - 1)), out.data_ptr())
+    _check(st, "fftenkf_analyze_noalloc")
     return out
 
 

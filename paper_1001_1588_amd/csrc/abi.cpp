@@ -691,8 +691,10 @@ int check_mlp(const fftenkf_mlp* m, bool device) {
   return device ? check_pointers(w, 8) : FFTENKF_OK;
 }
 
+// ws_static: the workspace is the library's static scratch array (not a HIP
+// allocation, so it is left out of the device-pointer check).
 int analyze_impl(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed, const fftenkf_mlp* mlp,
-                 const void* lam, void* out) {
+                 const void* lam, void* out, bool ws_static = false) {
   try {
     Plan plan;
     int st = validate_shape(e, &plan);
@@ -725,7 +727,10 @@ int analyze_impl(const fftenkf_ens* e, const void* data, const void* R_spec, uin
       st = check_mlp(mlp, false);
       if (st != FFTENKF_OK) return st;
     }
-    st = check_pointers(ptrs, np);
+    Ptr dev_ptrs[np];
+    for (int i = 0; i < np; ++i) dev_ptrs[i] = ptrs[i];
+    if (ws_static) dev_ptrs[4].p = nullptr;
+    st = check_pointers(dev_ptrs, np);
     if (st == FFTENKF_OK && mlp != nullptr) st = check_mlp(mlp, true);
     const size_t plane = (size_t)e->ny * (e->nx / 2 + 1);
     hipStream_t stream = static_cast<hipStream_t>(e->stream);
@@ -739,12 +744,82 @@ int analyze_impl(const fftenkf_ens* e, const void* data, const void* R_spec, uin
   }
 }
 
+// ---- static scratch of the entry point that allocates nothing
+//
+// One array of kScratchBytes in static device memory per device, used as the
+// workspace of fftenkf_analyze_noalloc.  The array's name is a host-side
+// stand-in: its address on a device comes from hipGetSymbolAddress with that
+// device current, once per device, and only that address is ever passed on.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kScratchDevices];
+
+}  // namespace
+}  // namespace fftenkf
+
+static __device__ __align__(256) unsigned char scratch[fftenkf::kScratchBytes];
+
+namespace fftenkf {
+namespace {
+
+// The scratch array's address on the current device (set up on the first call
+// on each device, together with that device's twiddle tables).
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "hipGetDevice: %s", hipGetErrorString(err));
+  if (dev < 0 || dev >= kScratchDevices) return fail(FFTENKF_EDEVICE, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[dev] == nullptr) {
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess || p == nullptr)
+      return fail(FFTENKF_EDEVICE, "scratch address: %s", hipGetErrorString(err));
+    const void* tab = nullptr;
+    err = twiddle_table(FFTENKF_F32, &tab);
+    if (err == hipSuccess) err = twiddle_table(FFTENKF_F64, &tab);
+    if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return FFTENKF_OK;
+}
+
 }  // namespace
 }  // namespace fftenkf
 
 using namespace fftenkf;
 
 extern "C" {
+
+size_t fftenkf_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int fftenkf_analyze_noalloc(const fftenkf_ens* e, const void* data, const void* R_spec, uint64_t seed, void* out) {
+  try {
+    if (e == nullptr) return fail(FFTENKF_EINVAL, "ens is NULL");
+    // shape checks first (host only), with a stand-in workspace of any size
+    fftenkf_ens copy = *e;
+    copy.workspace = reinterpret_cast<void*>((uintptr_t)256);
+    copy.workspace_bytes = (size_t)-1;
+    Plan plan;
+    int st = validate_shape(&copy, &plan);
+    if (st != FFTENKF_OK) return st;
+    if (plan.ws_bytes > kScratchBytes)
+      return fail(FFTENKF_EINVAL,
+                  "%d members on a %d x %d grid need %zu bytes of workspace; the static scratch holds %zu "
+                  "(call fftenkf_analyze with a workspace instead)",
+                  e->n_members, e->ny, e->nx, plan.ws_bytes, kScratchBytes);
+    void* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != FFTENKF_OK) return st;
+    copy.workspace = ws;
+    copy.workspace_bytes = kScratchBytes;
+    return analyze_impl(&copy, data, R_spec, seed, nullptr, nullptr, out, true);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
 
 int fftenkf_max_members(int dtype) {
   if (dtype == FFTENKF_F32) return kMaxMembersF32;

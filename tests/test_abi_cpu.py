@@ -246,3 +246,19 @@ def test_large_finite_r_scalar_accepted_by_validation(built_lib):
     e = _ens(r_scalar=1e39, dtype=_lib.F64, workspace_bytes=1 << 30)
     assert call(e) != _lib.OK
     assert "r_scalar" not in _lib.lib().fftenkf_last_error().decode()
+
+
+def test_noalloc_entry_point_limits(built_lib):
+    """The entry point that allocates nothing: its static scratch is 64 MiB;
+    shapes whose workspace exceeds it, and the usual shape errors, are rejected
+    before any device call (these pointers are not device memory)."""
+    lib = _lib.lib()
+    assert lib.fftenkf_noalloc_max_bytes() == 64 << 20
+    big = _ens(n_members=20, ny=2048, nx=2048, workspace=None, workspace_bytes=0)
+    assert lib.fftenkf_analyze_noalloc(ctypes.byref(big), 0x200000, None, 1, 0x300000) == _lib.EINVAL
+    assert "static scratch" in lib.fftenkf_last_error().decode()
+    assert lib.fftenkf_analyze_noalloc(None, 0x200000, None, 1, 0x300000) == _lib.EINVAL
+    bad = _ens(ny=12, workspace=None, workspace_bytes=0)
+    assert lib.fftenkf_analyze_noalloc(ctypes.byref(bad), 0x200000, None, 1, 0x300000) == _lib.EUNSUPPORTED
+    # the largest float32 member count that fits on a 1024 x 1024 grid is 13
+    assert lib.fftenkf_workspace_bytes(13, 1024, 1024, 0) <= 64 << 20 < lib.fftenkf_workspace_bytes(14, 1024, 1024, 0)
