@@ -11,7 +11,12 @@ Filter with application to a coupled atmosphere-wildland fire model":
 * enkf.py   -- O1, the spectral form (eq. (2) and eq. (3)), and O2, the dense
                form (eq. (1) with the circulant lag-averaged sample covariance);
 * learned.py -- the learned spectral covariance: a per-wavenumber perceptron
-               whose estimate replaces the c_hat of eq. (2) in eq. (3).
+               whose estimate replaces the c_hat of eq. (2) in eq. (3);
+* multiblock.py -- the multi-block state of Section 2.2, block 1 observed;
+* morph.py  -- the extended state of the morphing EnKF (Section 2.2, eq. (9)):
+               several observed fields with the cross-covariances among
+               them neglected;
+* dst.py    -- the analysis in the real sine basis (Section 4).
 
 Only the tests, the smoke check and the benchmark's CPU baseline may import
 this package.  It shares no code with the HIP path and imports nothing from it.

@@ -16,7 +16,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["test_oracle_dft.py", "test_oracle_variance.py", "test_oracle_update.py", "test_oracle_rng.py",
              "test_oracle_learned.py", "test_oracle_multiblock.py", "test_oracle_dst.py",
-             "test_oracle_degenerate.py"]
+             "test_oracle_degenerate.py", "test_oracle_morph.py"]
 
 MUTANTS = [
     ("enkf.py", "sum(axis=0) / (N - 1)", "sum(axis=0) / N"),
@@ -62,6 +62,12 @@ MUTANTS = [
     # the plausible mistake is forgetting both
     ("multiblock.py", "dj = sj - sj.mean(axis=0, keepdims=True)\n    d1 = s1 - s1.mean(axis=0, keepdims=True)",
      "dj = sj\n    d1 = s1"),
+    ("morph.py", "upd = upd + G[None] * innov[:, o]", "upd = upd + G[None] * innov[:, 0]"),
+    ("morph.py", "cjo = cross_spectrum(u_hat[:, j], u_hat[:, o])", "cjo = cross_spectrum(u_hat[:, o], u_hat[:, j])"),
+    ("morph.py", "np.uint64(0), np.uint64(o)), key)", "np.uint64(0), np.uint64(0)), key)"),
+    ("morph.py", "G = np.where(den[o] < tiny, 0.0, cjo / np.where(den[o] < tiny, 1.0, den[o]))",
+     "G = np.where(den[0] < tiny, 0.0, cjo / np.where(den[0] < tiny, 1.0, den[0]))"),
+    ("morph.py", "if a != b and a < K and b < K:", "if False:"),
 ]
 
 
