@@ -189,6 +189,42 @@ size_t fftenkf_workspace_bytes_multi(int n_members, int n_blocks, int ny, int nx
 int fftenkf_max_members_multi(int dtype);
 
 /*
+ * The FFT EnKF step of the morphing EnKF (Section 2.2, eq. (9)): the analysis
+ * of an extended state of M blocks whose first K (1 <= K <= 3) are observed,
+ * each by its own data d_o and stationary error R_o, with the
+ * cross-covariances among the observed blocks neglected, so that their
+ * covariance is K diagonal matrices in the frequency domain (in the paper,
+ * the extended state (T, r(1), .., r(M)) with T_x, T_y and r(1) observed).
+ * Per bin:
+ *   observed block o:   u^(o)a_k = u^(o)_k + c^(oo) / (c^(oo) + R_o) (d_o + e_ko - u^(o)_k),
+ *   unobserved block j: u^(j)a_k = u^(j)_k + sum_o c^(jo) / (c^(oo) + R_o) (d_o + e_ko - u^(o)_k),
+ * with c^(oo) from eq. (2) and c^(jo) from eq. (7) (conjugate on the observed
+ * factor), and no update from field o where c^(oo) + R_o is below the smallest
+ * normal number.  e_ko ~ N(0, R_o), independent across o, follows the
+ * convention of fftenkf_analyze with the fourth Philox counter word set to o
+ * (so o = 0 draws the single-block stream).  With K = 1 this is
+ * fftenkf_analyze_multi.  The registration that produces the extended state
+ * and the inverse morphing transform are the caller's.
+ *   ens->members, out : [N][M][ny][nx]  (member-major extended states)
+ *   data              : [K][ny][nx], block o observed by data[o]
+ *   R_spec            : [K][ny][nx/2+1] eigenvalues of each R_o, or NULL to
+ *                       use r_obs (host array of K doubles, R_o = r_obs[o] I;
+ *                       each >= 0 and finite in the working precision)
+ *   workspace         : fftenkf_workspace_bytes_morph(N, M, K, ny, nx, dtype) bytes
+ * 2 <= N <= fftenkf_max_members_morph(dtype, K), 1 <= K <= min(3, M) and
+ * M <= 64; other rules (alignment, overlap, in place, errors) as for
+ * fftenkf_analyze.
+ */
+int fftenkf_analyze_morph(const fftenkf_ens* ens, int n_blocks, int n_obs, const void* data, const void* R_spec,
+                          const double* r_obs, uint64_t seed, void* out);
+
+/* Workspace bytes of fftenkf_analyze_morph; 0 if the arguments are invalid. */
+size_t fftenkf_workspace_bytes_morph(int n_members, int n_blocks, int n_obs, int ny, int nx, int dtype);
+
+/* Largest N of fftenkf_analyze_morph for a dtype and number of observed blocks (0 if invalid). */
+int fftenkf_max_members_morph(int dtype, int n_obs);
+
+/*
  * A batch of independent analyses (eq. (3) with eq. (2), exactly as
  * fftenkf_analyze, one per filter) with one member count and dtype but grids
  * of any supported sizes.  Filters on the same grid share launches: each of the

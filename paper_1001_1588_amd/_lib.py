@@ -98,6 +98,12 @@ EXPORTS = {
     "fftenkf_workspace_bytes_multi": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                         ctypes.c_int]),
     "fftenkf_max_members_multi": (ctypes.c_int, [ctypes.c_int]),
+    "fftenkf_analyze_morph": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_uint64,
+                                             ctypes.c_void_p]),
+    "fftenkf_workspace_bytes_morph": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                        ctypes.c_int, ctypes.c_int]),
+    "fftenkf_max_members_morph": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "fftenkf_debug_fft2": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "fftenkf_debug_learned_spectrum": (ctypes.c_int, [ctypes.POINTER(Ens), ctypes.c_void_p, ctypes.POINTER(Mlp),
                                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -220,6 +226,36 @@ def analyze_multi(ens: torch.Tensor, data: torch.Tensor, R_spec: Union[torch.Ten
     st = lib().fftenkf_analyze_multi(ctypes.byref(e), M, data.data_ptr(), _ptr(R_t),
                                      ctypes.c_uint64(seed & (2**64 - 1)), out.data_ptr())
     _check(st, "fftenkf_analyze_multi")
+    return out
+
+
+def analyze_morph(ens: torch.Tensor, data: torch.Tensor, R, seed: int, out: Optional[torch.Tensor] = None,
+                  workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The extended-state analysis of the morphing EnKF: ens [N, M, ny, nx]
+    member-major, data [K, ny, nx] observing blocks 0 .. K-1; R is a
+    [K, ny, nx//2+1] tensor of eigenvalues or a sequence of K floats."""
+    if ens.dim() != 4 or not ens.is_cuda or not ens.is_contiguous():
+        raise ValueError("ens must be a contiguous device tensor [N, M, ny, nx]")
+    if data.dim() != 3 or not data.is_contiguous():
+        raise ValueError("data must be a contiguous [K, ny, nx] tensor")
+    N, M, ny, nx = ens.shape
+    K = int(data.shape[0])
+    code = _dtype_code(ens)
+    if isinstance(R, torch.Tensor):
+        R_t, r_arr = R, None
+    else:
+        R_t, r_arr = None, (ctypes.c_double * K)(*[float(x) for x in R])
+    if workspace is None:
+        need = int(lib().fftenkf_workspace_bytes_morph(N, M, K, ny, nx, code))
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=ens.device)
+    e = Ens(n_members=N, ny=ny, nx=nx, dtype=code, members=ens.data_ptr(), workspace=workspace.data_ptr(),
+            workspace_bytes=workspace.numel(), stream=torch.cuda.current_stream(ens.device).cuda_stream,
+            r_scalar=0.0)
+    if out is None:
+        out = torch.empty_like(ens)
+    st = lib().fftenkf_analyze_morph(ctypes.byref(e), M, K, data.data_ptr(), _ptr(R_t), r_arr,
+                                     ctypes.c_uint64(seed & (2**64 - 1)), out.data_ptr())
+    _check(st, "fftenkf_analyze_morph")
     return out
 
 

@@ -63,11 +63,13 @@ hipError_t launch_k2_batch_f32_n24(const BatchArgs&, hipStream_t);
 hipError_t launch_k2_batch_f64_n4(const BatchArgs&, hipStream_t);
 hipError_t launch_k2_batch_f64_n8(const BatchArgs&, hipStream_t);
 
-hipError_t launch_k6_f32(const K6Args&, hipStream_t);
-hipError_t launch_k6_f64(const K6Args&, hipStream_t);
+hipError_t launch_k10_f32_k1(const K10Args&, hipStream_t);
+hipError_t launch_k10_f32_k3(const K10Args&, hipStream_t);
+hipError_t launch_k10_f64(const K10Args&, hipStream_t);
 
-hipError_t launch_k6(const K6Args& a, int dtype, hipStream_t s) {
-  return dtype == FFTENKF_F32 ? launch_k6_f32(a, s) : launch_k6_f64(a, s);
+hipError_t launch_k10(const K10Args& a, int dtype, hipStream_t s) {
+  if (dtype == FFTENKF_F64) return launch_k10_f64(a, s);
+  return a.K == 1 ? launch_k10_f32_k1(a, s) : launch_k10_f32_k3(a, s);
 }
 
 hipError_t launch_k2_f64(const K2Args& a, hipStream_t s) {
@@ -456,19 +458,28 @@ int run_fft2(const fftenkf_ens* e, const Plan& plan, int inverse, const void* sp
   return FFTENKF_OK;
 }
 
-// Shape and workspace checks of the multi-block analysis; the plan covers the
-// N * M member fields and d.
-int validate_multi(const fftenkf_ens* e, int M, Plan* plan) {
+// Largest N of the sweep with K observed blocks.
+int max_members_observed(int dtype, int K) {
+  if (dtype == FFTENKF_F32) return K == 1 ? kMaxMembersMultiF32 : kMaxMembersObsF32;
+  if (dtype == FFTENKF_F64) return K == 1 ? kMaxMembersMultiF64 : kMaxMembersObsF64;
+  return 0;
+}
+
+// Shape and workspace checks of an M-block state with K observed blocks; the
+// plan covers the N * M member fields and the K data fields.
+int validate_observed(const fftenkf_ens* e, int M, int K, Plan* plan) {
   if (e == nullptr) return fail(FFTENKF_EINVAL, "ens is NULL");
   if (e->dtype != FFTENKF_F32 && e->dtype != FFTENKF_F64) return fail(FFTENKF_EINVAL, "dtype %d is not 0 (f32) or 1 (f64)", e->dtype);
   if (e->n_members < 2) return fail(FFTENKF_EINVAL, "n_members = %d, eq. (2) needs N >= 2", e->n_members);
   if (M < 1 || M > kMaxStateBlocks) return fail(FFTENKF_EINVAL, "n_blocks = %d outside [1, %d]", M, kMaxStateBlocks);
+  if (K < 1 || K > kMaxObserved || K > M)
+    return fail(FFTENKF_EINVAL, "n_obs = %d outside [1, min(%d, n_blocks = %d)]", K, kMaxObserved, M);
   if (!pow2_in_range(e->ny) || !pow2_in_range(e->nx))
     return fail(FFTENKF_EUNSUPPORTED, "grid %d x %d: each side must be a power of two in [8, 4096]", e->ny, e->nx);
-  if (e->n_members > fftenkf_max_members_multi(e->dtype))
-    return fail(FFTENKF_EUNSUPPORTED, "n_members = %d exceeds %d for the multi-block analysis", e->n_members,
-                fftenkf_max_members_multi(e->dtype));
-  *plan = make_plan(e->n_members * M, e->ny, e->nx, e->dtype);
+  if (e->n_members > max_members_observed(e->dtype, K))
+    return fail(FFTENKF_EUNSUPPORTED, "n_members = %d exceeds %d for %d observed block(s)", e->n_members,
+                max_members_observed(e->dtype, K), K);
+  *plan = make_plan(e->n_members * M + K - 1, e->ny, e->nx, e->dtype);
   if (e->members == nullptr) return fail(FFTENKF_EINVAL, "members is NULL");
   if (e->workspace == nullptr) return fail(FFTENKF_EINVAL, "workspace is NULL");
   if (e->workspace_bytes < plan->ws_bytes)
@@ -478,9 +489,10 @@ int validate_multi(const fftenkf_ens* e, int M, Plan* plan) {
   return FFTENKF_OK;
 }
 
-// Sweep 1 over the N * M member fields and d, the multi-block spectral sweep, sweep 3.
-int run_multi(const fftenkf_ens* e, int M, const Plan& plan, const void* data, const void* R_spec, uint64_t seed,
-              void* out) {
+// Sweep 1 over the N * M member fields and the K data fields, the sweep of
+// the observed-block state, sweep 3 over the member fields.
+int run_observed(const fftenkf_ens* e, int M, int K, const Plan& plan, const void* data, const void* R_spec,
+                 const double* r_obs, uint64_t seed, void* out) {
   if (t_fail_next != 0) {
     const int st = t_fail_next;
     t_fail_next = 0;
@@ -497,36 +509,81 @@ int run_multi(const fftenkf_ens* e, int M, const Plan& plan, const void* data, c
   if (!(t_events_on && t_nevents == 4)) t_events_on = false;
   err = mark(0, stream);
   K1Args a1{e->members, data, fields, e->ny, e->nx, plan.R, plan.L, ws_main, ws_nyq, tab};
+  a1.n_data = K;
   if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
   if (err == hipSuccess) err = mark(1, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 1 launch: %s", hipGetErrorString(err));
-  K6Args a6{};
-  a6.ws_main = ws_main;
-  a6.ws_nyq = ws_nyq;
-  a6.R_spec = R_spec;
-  a6.r_scalar = e->r_scalar;
-  a6.N = e->n_members;
-  a6.M = M;
-  a6.ny = e->ny;
-  a6.nx = e->nx;
-  a6.R = plan.R;
-  a6.L = plan.L;
-  a6.C = plan.C;
-  a6.units_main = plan.units_main;
-  a6.units_total = plan.units_total;
-  a6.group_xcd = plan.group_xcd;
-  a6.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
-  a6.key1 = (uint32_t)(seed >> 32);
-  a6.tab = tab;
-  err = launch_k6(a6, e->dtype, stream);
+  K10Args a10{};
+  a10.ws_main = ws_main;
+  a10.ws_nyq = ws_nyq;
+  a10.R_spec = R_spec;
+  for (int o = 0; o < K; ++o) a10.r_obs[o] = r_obs != nullptr ? r_obs[o] : 0.0;
+  a10.N = e->n_members;
+  a10.M = M;
+  a10.K = K;
+  a10.ny = e->ny;
+  a10.nx = e->nx;
+  a10.R = plan.R;
+  a10.L = plan.L;
+  a10.C = plan.C;
+  a10.units_main = plan.units_main;
+  a10.units_total = plan.units_total;
+  a10.group_xcd = plan.group_xcd;
+  a10.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  a10.key1 = (uint32_t)(seed >> 32);
+  a10.tab = tab;
+  err = launch_k10(a10, e->dtype, stream);
   if (err == hipSuccess) err = mark(2, stream);
-  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "multi-block sweep launch: %s", hipGetErrorString(err));
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "observed-block sweep launch: %s", hipGetErrorString(err));
   K3Args a3{ws_main, ws_nyq, fields, e->ny, e->nx, plan.R, plan.L, out, tab};
   err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
   if (err == hipSuccess) err = mark(3, stream);
   t_events_on = false;
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 3 launch: %s", hipGetErrorString(err));
   return FFTENKF_OK;
+}
+
+// Argument checks and dispatch of the state with K observed blocks.  R per
+// observed block: R_spec ([K][ny][nx/2+1]) or, when it is NULL, r_obs[o].
+int analyze_observed(const fftenkf_ens* e, int M, int K, const void* data, const void* R_spec, const double* r_obs,
+                     uint64_t seed, void* out) {
+  Plan plan;
+  int st = validate_observed(e, M, K, &plan);
+  if (st != FFTENKF_OK) return st;
+  if (data == nullptr) return fail(FFTENKF_EINVAL, "data is NULL");
+  if (out == nullptr) return fail(FFTENKF_EINVAL, "out is NULL");
+  if (misaligned(data, 16) || misaligned(out, 16) || (R_spec != nullptr && misaligned(R_spec, 16)))
+    return fail(FFTENKF_EINVAL, "data, R_spec and out must be 16-byte aligned");
+  if (R_spec == nullptr) {
+    if (r_obs == nullptr) return fail(FFTENKF_EINVAL, "R_spec and r_obs are both NULL");
+    for (int o = 0; o < K; ++o) {
+      char prefix[48];
+      snprintf(prefix, sizeof(prefix), "observed block %d: ", o);
+      if ((st = check_r_scalar(r_obs[o], e->dtype, prefix)) != FFTENKF_OK) return st;
+    }
+  }
+  const size_t s = dsize(e->dtype);
+  const size_t field = (size_t)e->ny * e->nx * s;
+  const size_t ens_b = field * e->n_members * M;
+  const size_t rs_b = (size_t)e->ny * (e->nx / 2 + 1) * s * K;
+  const Ptr ptrs[] = {{e->members, ens_b, "members"},
+                      {data, field * K, "data"},
+                      {R_spec, rs_b, "R_spec"},
+                      {out, ens_b, "out"},
+                      {e->workspace, plan.ws_bytes, "workspace"}};
+  for (int i = 0; i < 5; ++i)
+    for (int j = i + 1; j < 5; ++j) {
+      if (ptrs[i].p == nullptr || ptrs[j].p == nullptr) continue;
+      const bool in_place = (i == 0 && j == 3 && ptrs[i].p == ptrs[j].p);
+      if (!in_place && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
+        return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
+    }
+  st = check_pointers(ptrs, 5);
+  if (st == FFTENKF_OK)
+    st = check_spectrum_values(R_spec, (size_t)e->ny * (e->nx / 2 + 1) * K, e->dtype,
+                               static_cast<hipStream_t>(e->stream), "R_spec");
+  if (st != FFTENKF_OK) return st;
+  return run_observed(e, M, K, plan, data, R_spec, r_obs, seed, out);
 }
 
 hipError_t launch_k2_batch(const BatchArgs& b, int dtype, hipStream_t s) {
@@ -994,52 +1051,38 @@ int fftenkf_debug_fft2(const fftenkf_ens* e, int inverse, const void* spectra, v
   }
 }
 
-int fftenkf_max_members_multi(int dtype) {
-  if (dtype == FFTENKF_F32) return kMaxMembersMultiF32;
-  if (dtype == FFTENKF_F64) return kMaxMembersMultiF64;
-  return 0;
-}
+int fftenkf_max_members_multi(int dtype) { return max_members_observed(dtype, 1); }
 
 size_t fftenkf_workspace_bytes_multi(int n_members, int n_blocks, int ny, int nx, int dtype) {
-  if ((dtype != FFTENKF_F32 && dtype != FFTENKF_F64) || n_members < 2 || n_blocks < 1 || n_blocks > kMaxStateBlocks ||
-      !pow2_in_range(ny) || !pow2_in_range(nx))
-    return 0;
-  return make_plan(n_members * n_blocks, ny, nx, dtype).ws_bytes;
+  return fftenkf_workspace_bytes_morph(n_members, n_blocks, 1, ny, nx, dtype);
 }
 
 int fftenkf_analyze_multi(const fftenkf_ens* e, int n_blocks, const void* data, const void* R_spec, uint64_t seed,
                           void* out) {
   try {
-    Plan plan;
-    int st = validate_multi(e, n_blocks, &plan);
-    if (st != FFTENKF_OK) return st;
-    if (data == nullptr) return fail(FFTENKF_EINVAL, "data is NULL");
-    if (out == nullptr) return fail(FFTENKF_EINVAL, "out is NULL");
-    if (misaligned(data, 16) || misaligned(out, 16) || (R_spec != nullptr && misaligned(R_spec, 16)))
-      return fail(FFTENKF_EINVAL, "data, R_spec and out must be 16-byte aligned");
-    if (R_spec == nullptr && (st = check_r_scalar(e->r_scalar, e->dtype, "")) != FFTENKF_OK) return st;
-    const size_t s = dsize(e->dtype);
-    const size_t field = (size_t)e->ny * e->nx * s;
-    const size_t ens_b = field * e->n_members * n_blocks;
-    const size_t rs_b = (size_t)e->ny * (e->nx / 2 + 1) * s;
-    const Ptr ptrs[] = {{e->members, ens_b, "members"},
-                        {data, field, "data"},
-                        {R_spec, rs_b, "R_spec"},
-                        {out, ens_b, "out"},
-                        {e->workspace, plan.ws_bytes, "workspace"}};
-    for (int i = 0; i < 5; ++i)
-      for (int j = i + 1; j < 5; ++j) {
-        if (ptrs[i].p == nullptr || ptrs[j].p == nullptr) continue;
-        const bool in_place = (i == 0 && j == 3 && ptrs[i].p == ptrs[j].p);
-        if (!in_place && overlaps(ptrs[i].p, ptrs[i].bytes, ptrs[j].p, ptrs[j].bytes))
-          return fail(FFTENKF_EINVAL, "%s overlaps %s", ptrs[i].name, ptrs[j].name);
-      }
-    st = check_pointers(ptrs, 5);
-    if (st == FFTENKF_OK)
-      st = check_spectrum_values(R_spec, (size_t)e->ny * (e->nx / 2 + 1), e->dtype,
-                                 static_cast<hipStream_t>(e->stream), "R_spec");
-    if (st != FFTENKF_OK) return st;
-    return run_multi(e, n_blocks, plan, data, R_spec, seed, out);
+    const double r = e != nullptr ? e->r_scalar : 0.0;
+    return analyze_observed(e, n_blocks, 1, data, R_spec, &r, seed, out);
+  } catch (...) {
+    return fail(FFTENKF_EDEVICE, "internal error");
+  }
+}
+
+int fftenkf_max_members_morph(int dtype, int n_obs) {
+  if (n_obs < 1 || n_obs > kMaxObserved) return 0;
+  return max_members_observed(dtype, n_obs);
+}
+
+size_t fftenkf_workspace_bytes_morph(int n_members, int n_blocks, int n_obs, int ny, int nx, int dtype) {
+  if ((dtype != FFTENKF_F32 && dtype != FFTENKF_F64) || n_members < 2 || n_blocks < 1 || n_blocks > kMaxStateBlocks ||
+      n_obs < 1 || n_obs > kMaxObserved || n_obs > n_blocks || !pow2_in_range(ny) || !pow2_in_range(nx))
+    return 0;
+  return make_plan(n_members * n_blocks + n_obs - 1, ny, nx, dtype).ws_bytes;
+}
+
+int fftenkf_analyze_morph(const fftenkf_ens* e, int n_blocks, int n_obs, const void* data, const void* R_spec,
+                          const double* r_obs, uint64_t seed, void* out) {
+  try {
+    return analyze_observed(e, n_blocks, n_obs, data, R_spec, r_obs, seed, out);
   } catch (...) {
     return fail(FFTENKF_EDEVICE, "internal error");
   }

@@ -31,7 +31,7 @@ struct K1Geom {
 template <typename T, int NX, int R, int SB, bool SINE>
 __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* __restrict__ data, int N, int ny,
                                         int L, V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq,
-                                        const V2<T>* __restrict__ tab, unsigned block) {
+                                        const V2<T>* __restrict__ tab, unsigned block, int n_data = 1) {
   using Geo = K1Geom<T, NX>;
   constexpr int P = Geo::P, TF = Geo::TF, G = Geo::G;
   constexpr int H = R / 2;
@@ -43,10 +43,10 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
   const int g = tid / TF;
   const int t = tid - g * TF;
   const int tile = block * G + g;
-  const bool active = tile < (N + 1) * L;
+  const bool active = tile < (N + n_data) * L;
   const int f = active ? tile / L : 0;
   const int y1 = active ? tile - f * L : 0;
-  const T* __restrict__ src = (f < N) ? members + (size_t)f * ny * NX : data;
+  const T* __restrict__ src = (f < N) ? members + (size_t)f * ny * NX : data + (size_t)(f - N) * ny * NX;
   V2<T>* my = lds + g * SB * SEQP;
   LdsPair lp{my, nullptr, 0, 0};
 
@@ -165,8 +165,8 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
 template <typename T, int NX, int R, int SB, bool SINE>
 __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
     const T* __restrict__ members, const T* __restrict__ data, int N, int ny, int L,
-    V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq, const V2<T>* __restrict__ tab) {
-  k1_body<T, NX, R, SB, SINE>(members, data, N, ny, L, ws_main, ws_nyq, tab, blockIdx.x);
+    V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq, const V2<T>* __restrict__ tab, int n_data) {
+  k1_body<T, NX, R, SB, SINE>(members, data, N, ny, L, ws_main, ws_nyq, tab, blockIdx.x, n_data);
 }
 
 // A batch of analyses on one grid: blockIdx.y selects the analysis.
@@ -199,16 +199,16 @@ template <typename T, int NX, int R>
 hipError_t launch_k1_shape(const K1Args& a, hipStream_t st) {
   using Geo = K1Geom<T, NX>;
   constexpr int SB = k1_sb<T, NX, R>();
-  const int tiles = (a.N + 1) * a.L;
+  const int tiles = (a.N + a.n_data) * a.L;
   const dim3 grid((tiles + Geo::G - 1) / Geo::G), block(Geo::threads);
   if (a.sine)
     hipLaunchKernelGGL((k1_forward<T, NX, R, SB, true>), grid, block, 0, st, static_cast<const T*>(a.members),
                        static_cast<const T*>(a.data), a.N, a.ny, a.L, static_cast<V2<T>*>(a.ws_main),
-                       static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab));
+                       static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab), a.n_data);
   else
     hipLaunchKernelGGL((k1_forward<T, NX, R, SB, false>), grid, block, 0, st, static_cast<const T*>(a.members),
                        static_cast<const T*>(a.data), a.N, a.ny, a.L, static_cast<V2<T>*>(a.ws_main),
-                       static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab));
+                       static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab), a.n_data);
   return hipGetLastError();
 }
 

@@ -23,12 +23,13 @@ namespace fftenkf {
 
 struct K1Args {
   const void* members;  // [N][ny][nx]
-  const void* data;     // [ny][nx]
+  const void* data;     // [n_data][ny][nx]: fields N .. N + n_data - 1
   int N, ny, nx, R, L;
   void* ws_main;
   void* ws_nyq;
   const void* tab;  // W_4096^k table of dtype's complex type (device)
-  int sine;         // 1: transform the sine-basis reordering of the fields (dst_rho)
+  int sine = 0;     // 1: transform the sine-basis reordering of the fields (dst_rho)
+  int n_data = 1;   // data fields after the N member fields
 };
 
 // K2_STATS: forward transforms and eq. (2) only -- writes c_hat to chat_map,
@@ -71,14 +72,16 @@ struct K2Args {
   const void* tab;
 };
 
-// Multi-block spectral sweep: member k of block j is field k * M + j, d is
-// field N * M; the other fields as in K2Args.
-struct K6Args {
+// Spectral sweep of an M-block state whose first K blocks are observed
+// (k10_observed.hpp): member k of block j is field k * M + j, the data of
+// observed block o is field N * M + o; the other fields as in K2Args.
+constexpr int kMaxObserved = 3;
+struct K10Args {
   void* ws_main;
   void* ws_nyq;
-  const void* R_spec;  // [ny][nx/2+1] or nullptr
-  double r_scalar;
-  int N, M, ny, nx, R, L, C, units_main, units_total, group_xcd;
+  const void* R_spec;          // [K][ny][nx/2+1] or nullptr
+  double r_obs[kMaxObserved];  // R_o = r_obs[o] I when R_spec is nullptr
+  int N, M, K, ny, nx, R, L, C, units_main, units_total, group_xcd;
   uint32_t key0, key1;
   const void* tab;
 };
@@ -125,16 +128,20 @@ constexpr int k2_threads_target = 256;
 // Largest member count held in registers by the fused spectral sweep.
 constexpr int kMaxMembersF32 = 24;
 constexpr int kMaxMembersF64 = 8;
-// The multi-block sweep holds two register sets of members.
+// The sweep of a state with K observed blocks holds K + 1 register sets of
+// members: up to 12 (float32) or 4 (float64) members with one observed block,
+// 8 or 4 with two or three.
 constexpr int kMaxMembersMultiF32 = 12;
 constexpr int kMaxMembersMultiF64 = 4;
+constexpr int kMaxMembersObsF32 = 8;
+constexpr int kMaxMembersObsF64 = 4;
 constexpr int kMaxStateBlocks = 64;  // blocks of the multi-block analysis
 
 hipError_t launch_k1_f32(const K1Args& a, hipStream_t s);
 hipError_t launch_k1_f64(const K1Args& a, hipStream_t s);
 hipError_t launch_k2_f32(const K2Args& a, hipStream_t s);
 hipError_t launch_k2_f64(const K2Args& a, hipStream_t s);
-hipError_t launch_k6(const K6Args& a, int dtype, hipStream_t s);
+hipError_t launch_k10(const K10Args& a, int dtype, hipStream_t s);
 hipError_t launch_k3_f32(const K3Args& a, hipStream_t s);
 hipError_t launch_k3_f64(const K3Args& a, hipStream_t s);
 
