@@ -32,8 +32,8 @@ SOURCES = {
     "k1_forward": COMMON + [CSRC + "k1_forward.hpp"],
     "k2_spectral": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "k2_spectral.hpp"],
     "k3_inverse": COMMON + [CSRC + "k1_forward.hpp", CSRC + "k3_inverse.hpp"],
-    "k6_multiblock": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "k2_spectral.hpp",
-                               CSRC + "k6_multiblock.hpp"],
+    "k10_observed": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "k2_spectral.hpp",
+                              CSRC + "k10_observed.hpp"],
     "k7_spectral_mlp": [CSRC + "kernels.hpp", CSRC + "k7_spectral_mlp.hip"],
     "dst_": [CSRC + "fft_core.hpp", CSRC + "kernels.hpp", CSRC + "philox.hpp", CSRC + "k9_dst.hip"],
 }

@@ -101,7 +101,7 @@ Workload: 4 blocks of 1024x1024, N = 10, float32, spectra (1+|k|^2/L_b^2)^-2 wit
 
 {hdr}
 {row(*first(('fftenkf::k1_forward<float, 1024, 8, 4, false>', 671744), ('fftenkf::k1_forward<float, 1024, 16, 8, false>', 335872)), 41*n1*4 + 41*h1)}
-{row(*first(('fftenkf::k6_multiblock<float, 128, 10>', 131328), ('fftenkf::k6_multiblock<float, 64, 10>', 131328)), 41*h1 + 1024*513*4 + 40*h1)}
+{row(*first(('fftenkf::k10_observed<float, 128, 10, 1>', 131328), ('fftenkf::k10_observed<float, 64, 10, 1>', 131328)), 41*h1 + 1024*513*4 + 40*h1)}
 {row(*first(('fftenkf::k3_inverse<float, 1024, 8, 4, false>', 655360), ('fftenkf::k3_inverse<float, 1024, 16, 8, false>', 327680)), 40*h1 + 40*n1*4)}
 '''
     out['sine2048_n20_sweeps.md'] = f'''# rocprofv3 summary: the analysis in the real sine basis on 2048x2048, N=20, float32
