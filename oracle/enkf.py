@@ -63,25 +63,35 @@ def spectral_noise(seed: int, N: int, ny: int, nx: int) -> np.ndarray:
 
     z_hat is distributed as the unitary DFT of real white noise N(0, I):
       * generic bins: (a + i b) / sqrt(2);
-      * self-conjugate bins: a (real);
+      * self-conjugate bins: real, a in the kx = 0 column and b in the
+        kx = nx/2 column, both from the kx = 0 bin's draw (the two real bins of
+        a row ky in {0, ny/2} share one Box-Muller pair, as the real and
+        imaginary parts of a generic bin do);
       * mirrored bins (see special_masks): the conjugate of the generating bin
         (ny - ky, kx), so the field it represents is real.
     (a, b) = Box-Muller of two words of Philox4x32-10 with
       key     = (seed mod 2^32, seed div 2^32),
-      counter = (gy * (nx//2 + 1) + gx, k div 2, 0, 0), (gy, gx) the generating bin;
+      counter = (gy * (nx//2 + 1) + gx, k div 2, 0, 0), (gy, gx) the generating
+                bin (gx = 0 for both self-conjugate bins of a row);
       member k uses words (x0, x1) when k is even and (x2, x3) when k is odd.
     """
+    return _noise(seed, N, ny, nx, 0)
+
+
+def _noise(seed: int, N: int, ny: int, nx: int, word3: int) -> np.ndarray:
+    """spectral_noise with the fourth counter word set to word3."""
     nh = nx // 2 + 1
     ky, kx, mirrored, selfconj = special_masks(ny, nx)
     gy = np.where(mirrored, ny - ky, ky)
-    lin = (gy * nh + kx).astype(np.uint64)
+    nyq_sc = selfconj & (kx == nx // 2)
+    lin = (gy * nh + np.where(nyq_sc, 0, kx)).astype(np.uint64)
     key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
     z = np.empty((N, ny, nh), dtype=np.complex128)
     for k in range(N):
-        words = philox4x32((lin, np.uint64(k // 2), np.uint64(0), np.uint64(0)), key)
+        words = philox4x32((lin, np.uint64(k // 2), np.uint64(0), np.uint64(word3)), key)
         wa, wb = (words[0], words[1]) if k % 2 == 0 else (words[2], words[3])
         a, b = box_muller(wa, wb)
-        zk = np.where(selfconj, a + 0j, (a + 1j * b) / np.sqrt(2.0))
+        zk = np.where(selfconj, np.where(nyq_sc, b, a) + 0j, (a + 1j * b) / np.sqrt(2.0))
         z[k] = np.where(mirrored, np.conj(zk), zk)
     return z
 

@@ -37,28 +37,18 @@ from __future__ import annotations
 import numpy as np
 
 from . import dft
-from .enkf import spectral_gain, special_masks, tiny_for
+from .enkf import _noise, spectral_gain, tiny_for
 from .multiblock import circulant, cross_spectrum, lag_cross_covariance
-from .philox import box_muller, philox4x32
 
 
 def observed_noise(seed: int, N: int, K: int, ny: int, nx: int) -> np.ndarray:
     """Unit-variance spectral white noise z_hat[k, o, ky, kx] (half spectrum) for
     member k and observed field o: enkf.spectral_noise's convention with the
-    counter (generating bin, k div 2, 0, o)."""
+    fourth counter word o."""
     nh = nx // 2 + 1
-    ky, kx, mirrored, selfconj = special_masks(ny, nx)
-    gy = np.where(mirrored, ny - ky, ky)
-    lin = (gy * nh + kx).astype(np.uint64)
-    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
     z = np.empty((N, K, ny, nh), dtype=np.complex128)
     for o in range(K):
-        for k in range(N):
-            words = philox4x32((lin, np.uint64(k // 2), np.uint64(0), np.uint64(o)), key)
-            wa, wb = (words[0], words[1]) if k % 2 == 0 else (words[2], words[3])
-            a, b = box_muller(wa, wb)
-            zk = np.where(selfconj, a + 0j, (a + 1j * b) / np.sqrt(2.0))
-            z[k, o] = np.where(mirrored, np.conj(zk), zk)
+        z[:, o] = _noise(seed, N, ny, nx, o)
     return z
 
 

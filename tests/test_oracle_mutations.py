@@ -64,7 +64,8 @@ MUTANTS = [
      "dj = sj\n    d1 = s1"),
     ("morph.py", "upd = upd + G[None] * innov[:, o]", "upd = upd + G[None] * innov[:, 0]"),
     ("morph.py", "cjo = cross_spectrum(u_hat[:, j], u_hat[:, o])", "cjo = cross_spectrum(u_hat[:, o], u_hat[:, j])"),
-    ("morph.py", "np.uint64(0), np.uint64(o)), key)", "np.uint64(0), np.uint64(0)), key)"),
+    ("morph.py", "z[:, o] = _noise(seed, N, ny, nx, o)", "z[:, o] = _noise(seed, N, ny, nx, 0)"),
+    ("enkf.py", "np.where(nyq_sc, b, a) + 0j", "a + 0j"),
     ("morph.py", "G = np.where(den[o] < tiny, 0.0, cjo / np.where(den[o] < tiny, 1.0, den[o]))",
      "G = np.where(den[0] < tiny, 0.0, cjo / np.where(den[0] < tiny, 1.0, den[0]))"),
     ("morph.py", "if a != b and a < K and b < K:", "if False:"),

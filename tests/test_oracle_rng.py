@@ -94,6 +94,21 @@ def test_spectral_noise_statistics():
     assert stats.kstest(e.ravel(), "norm").pvalue > 1e-3
 
 
+def test_self_conjugate_bins_are_independent_unit_normals():
+    """The four real bins of the spectrum: each N(0, 1) across members and the
+    four mutually uncorrelated (the two of a row share one Box-Muller pair, whose
+    halves are independent); a mistake that reused one half for both bins of a
+    row would give correlation 1."""
+    ny, nx, N = 8, 8, 4000
+    z = enkf.spectral_noise(2024, N, ny, nx)
+    vals = np.stack([z[:, ky, kx].real for ky in (0, ny // 2) for kx in (0, nx // 2)])
+    assert np.all(np.abs(vals.var(axis=1) - 1) < 0.08)
+    c = np.corrcoef(vals)
+    assert np.max(np.abs(c - np.eye(4))) < 0.08
+    for v in vals:
+        assert stats.kstest(v, "norm").pvalue > 1e-3
+
+
 def test_perturbation_scaled_by_R_and_seed_dependent():
     ny = nx = 32
     R = np.full((ny, nx // 2 + 1), 0.05)
