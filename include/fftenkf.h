@@ -17,13 +17,15 @@
  * of eq. (1) are drawn in the frequency domain, e_hat_k = sqrt(R_spec) z_hat_k,
  * with z_hat_k distributed as the unitary DFT of real white noise:
  *   - generic bins: (a + i b) / sqrt(2);
- *   - the four self-conjugate bins (ky in {0, ny/2}, kx in {0, nx/2}): a;
+ *   - the four self-conjugate bins (ky in {0, ny/2}, kx in {0, nx/2}): a at
+ *     kx = 0 and b at kx = nx/2, both from the draw of the bin (ky, 0);
  *   - bins in the kx = 0 and kx = nx/2 columns with ky > ny/2: the conjugate of
  *     the value drawn for (ny - ky, kx).
  * (a, b) = Box-Muller(u1, u2) with u = (2 * (w >> 9) + 1) * 2^-24 for words w of
  * Philox4x32-10 (Salmon et al., SC'11), key = (seed mod 2^32, seed div 2^32),
  * counter = (gy * (nx/2 + 1) + gx, k div 2, 0, 0) for the generating bin
- * (gy, gx); member k takes words (x0, x1) if k is even, (x2, x3) if odd.
+ * (gy, gx) (gx = 0 for both self-conjugate bins of a row); member k takes
+ * words (x0, x1) if k is even, (x2, x3) if odd.
  * The squared deviations of eq. (2) are formed from u_hat_k - u_hat_0, the
  * same sum in exact arithmetic, so c_hat is exactly 0 when all members are
  * equal; the gain is 0 where c_hat + R_spec is below the smallest normal number
@@ -130,7 +132,10 @@ size_t fftenkf_workspace_bytes(int n_members, int ny, int nx, int dtype);
  * x_25 = log(1 + |k|) with |k| = sqrt(min(ky, ny-ky)^2 + kx^2); then
  * h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), h3 = relu(h2 W3 + b3),
  * y = h3 . w4 + b4 and lambda_hat = mu exp(y), mu = mean of c_hat over the
- * ny*(nx/2+1) stored bins.  The gain is lambda_hat / (lambda_hat + R_spec).
+ * ny*(nx/2+1) stored bins.  The gain is lambda_hat / (lambda_hat + R_spec);
+ * lambda_hat need not be even in ky, and in the kx = 0 and kx = nx/2 columns
+ * the update is that of the mean of the gains at (ky, kx) and (ny - ky, kx),
+ * which is what the inverse real transform of the updated half spectrum gives.
  * Inputs, weights and hidden activations are rounded to bfloat16 (nearest,
  * ties to even); products accumulate in float32 on the matrix cores.  Where mu
  * is not a positive normal float (no spread anywhere) the features do not
@@ -156,7 +161,9 @@ int fftenkf_analyze_learned(const fftenkf_ens* ens, const void* data, const void
 /* As fftenkf_analyze, with the covariance eigenvalues prescribed: lam is a
  * device [ny][nx/2+1] array of dtype (unitary DFT scale, the same scale as
  * R_spec) used in eq. (3) in place of the estimate of eq. (2), e.g. the known
- * spectrum of a twin experiment.  Same arguments and error behaviour. */
+ * spectrum of a twin experiment; in the kx = 0 and kx = nx/2 columns the gains
+ * at (ky, kx) and (ny - ky, kx) are averaged, as for fftenkf_analyze_learned.
+ * Same arguments and error behaviour. */
 int fftenkf_analyze_spectrum(const fftenkf_ens* ens, const void* data, const void* R_spec, uint64_t seed,
                              const void* lam, void* out);
 

@@ -109,9 +109,9 @@ size_t dsize(int dtype) { return dtype == FFTENKF_F64 ? 8 : 4; }
 
 // Grid factorisation ny = R * L and the unit shape of the spectral sweep.
 struct Plan {
-  int R, L, P, C, Cn, units_main, units_total, group_xcd;
-  size_t main_elems, nyq_elems;  // complex elements of the two spectral regions
-  size_t off_nyq, off_chat, off_lam, off_part;  // byte offsets in the workspace
+  int R, L, P, C, units, group_xcd;
+  size_t main_elems;                   // complex elements of the spectral region
+  size_t off_chat, off_lam, off_part;  // byte offsets in the workspace
   size_t ws_bytes;
 };
 
@@ -167,28 +167,24 @@ Plan make_plan(int N, int ny, int nx, int dtype) {
   if (c > nxh) c = nxh;
   if (c < 1) c = 1;
   p.C = c;
-  p.Cn = c;
-  p.units_main = p.R * (nxh / c);
-  p.units_total = p.units_main + (p.R + p.Cn - 1) / p.Cn;
+  p.units = p.R * (nxh / c);  // the Nyquist column is folded into kx = 0: no units of its own
   // group the units that share 128-byte lines on one XCD when segments are shorter
   const int seg = c * 2 * (int)dsize(dtype);
   const int g = seg < 128 ? 128 / seg : 1;
-  p.group_xcd = (g > 1 && (nxh / c) % g == 0 && p.units_main % (8 * g) == 0) ? g : 1;
+  p.group_xcd = (g > 1 && (nxh / c) % g == 0 && p.units % (8 * g) == 0) ? g : 1;
   const size_t nf = (size_t)N + 1;
   p.main_elems = nf * (size_t)ny * (size_t)nxh;
-  p.nyq_elems = nf * (size_t)ny;
   const size_t cplx = 2 * dsize(dtype);
   const size_t plane = (size_t)ny * (size_t)(nxh + 1) * dsize(dtype);
-  p.off_nyq = p.main_elems * cplx;
-  p.off_chat = round256(p.off_nyq + p.nyq_elems * cplx);
+  p.off_chat = round256(p.main_elems * cplx);
   p.off_lam = round256(p.off_chat + plane);
   p.off_part = round256(p.off_lam + plane);
-  p.ws_bytes = round256(p.off_part + (size_t)p.units_total * sizeof(float));
+  p.ws_bytes = round256(p.off_part + (size_t)p.units * sizeof(float));
   return p;
 }
 
-// The spectral sweep's share of K2Args: the plan's geometry and the byte sizes
-// of the two workspace regions (addressed with 32-bit offsets).
+// The spectral sweep's share of K2Args: the plan's geometry and the byte size
+// of the spectral region (addressed with 32-bit offsets).
 void set_k2_geometry(K2Args& a, const Plan& p, int N, int ny, int nx, int dtype) {
   const size_t cplx = 2 * dsize(dtype);
   a.N = N;
@@ -197,12 +193,9 @@ void set_k2_geometry(K2Args& a, const Plan& p, int N, int ny, int nx, int dtype)
   a.R = p.R;
   a.L = p.L;
   a.C = p.C;
-  a.Cn = p.Cn;
-  a.units_main = p.units_main;
-  a.units_total = p.units_total;
+  a.units = p.units;
   a.group_xcd = p.group_xcd;
   a.main_bytes = (uint32_t)(p.main_elems * cplx);
-  a.nyq_bytes = (uint32_t)(p.nyq_elems * cplx);
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -306,24 +299,22 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   const size_t cplx = 2 * dsize(e->dtype);
   char* ws = static_cast<char*>(e->workspace);
   void* ws_main = ws;
-  void* ws_nyq = ws + plan.off_nyq;
   (void)cplx;
   if (log_enabled())
     fprintf(stderr, "fftenkf: N=%d grid %dx%d dtype=%d R=%d L=%d C=%d units=%d group_xcd=%d mode=%d\n", e->n_members,
-            e->ny, e->nx, e->dtype, plan.R, plan.L, plan.C, plan.units_total, plan.group_xcd, mode);
+            e->ny, e->nx, e->dtype, plan.R, plan.L, plan.C, plan.units, plan.group_xcd, mode);
 
   const bool profiled = t_events_on && mode == K2_ANALYZE && t_nevents == (mlp != nullptr ? 6 : 4);
   if (!profiled) t_events_on = false;
   err = mark(0, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "profile event: %s", hipGetErrorString(err));
-  K1Args a1{e->members, data, e->n_members, e->ny, e->nx, plan.R, plan.L, ws_main, ws_nyq, tab};
+  K1Args a1{e->members, data, e->n_members, e->ny, e->nx, plan.R, plan.L, ws_main, tab};
   err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
   if (err == hipSuccess) err = mark(1, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 1 launch: %s", hipGetErrorString(err));
 
   K2Args a2{};
   a2.ws_main = ws_main;
-  a2.ws_nyq = ws_nyq;
   a2.R_spec = R_spec;
   a2.r_scalar = e->r_scalar;
   set_k2_geometry(a2, plan, e->n_members, e->ny, e->nx, e->dtype);
@@ -347,7 +338,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
     K7Args a7{};
     a7.chat = static_cast<const float*>(a2.chat_map);
     a7.partials = static_cast<const float*>(a2.partials);
-    a7.n_partials = plan.units_total;
+    a7.n_partials = plan.units;
     a7.ny = e->ny;
     a7.nx = e->nx;
     a7.W1 = mlp->W1;
@@ -375,7 +366,7 @@ int run(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 2 launch: %s", hipGetErrorString(err));
   if (mode != K2_ANALYZE) return FFTENKF_OK;
 
-  K3Args a3{ws_main, ws_nyq, e->n_members, e->ny, e->nx, plan.R, plan.L, out, tab};
+  K3Args a3{ws_main, e->n_members, e->ny, e->nx, plan.R, plan.L, out, tab};
   err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
   if (err == hipSuccess) err = mark(mlp != nullptr ? 5 : 3, stream);
   t_events_on = false;
@@ -424,21 +415,19 @@ int run_fft2(const fftenkf_ens* e, const Plan& plan, int inverse, const void* sp
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
   char* ws = static_cast<char*>(e->workspace);
   void* ws_main = ws;
-  void* ws_nyq = ws + plan.off_nyq;
   const double n = (double)e->ny * (double)e->nx;
   K2Args a2{};
   a2.ws_main = ws_main;
-  a2.ws_nyq = ws_nyq;
   a2.r_scalar = 1.0;
   set_k2_geometry(a2, plan, e->n_members, e->ny, e->nx, e->dtype);
   a2.chat_map = ws + plan.off_chat;
   a2.partials = ws + plan.off_part;
   a2.tab = tab;
-  K8Args a8{ws_main, ws_nyq, e->n_members, e->ny, e->nx, plan.R, plan.L, 0.0, nullptr};
+  K8Args a8{ws_main, e->n_members, e->ny, e->nx, plan.R, plan.L, 0.0, nullptr};
   auto k2 = [&]() { return e->dtype == FFTENKF_F32 ? launch_k2_f32(a2, stream) : launch_k2_f64(a2, stream); };
   if (!inverse) {
     // the members double as d: sweep 2 needs a data field, which is not used here
-    K1Args a1{e->members, e->members, e->n_members, e->ny, e->nx, plan.R, plan.L, ws_main, ws_nyq, tab};
+    K1Args a1{e->members, e->members, e->n_members, e->ny, e->nx, plan.R, plan.L, ws_main, tab};
     err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
     a2.mode = K2_STATS;
     if (err == hipSuccess) err = k2();
@@ -451,7 +440,7 @@ int run_fft2(const fftenkf_ens* e, const Plan& plan, int inverse, const void* sp
     err = launch_k8_scatter(a8, e->dtype, stream);
     a2.mode = K2_INVERSE;
     if (err == hipSuccess) err = k2();
-    K3Args a3{ws_main, ws_nyq, e->n_members, e->ny, e->nx, plan.R, plan.L, out, tab};
+    K3Args a3{ws_main, e->n_members, e->ny, e->nx, plan.R, plan.L, out, tab};
     if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
   }
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "transform launch: %s", hipGetErrorString(err));
@@ -504,18 +493,16 @@ int run_observed(const fftenkf_ens* e, int M, int K, const Plan& plan, const voi
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
   char* ws = static_cast<char*>(e->workspace);
   void* ws_main = ws;
-  void* ws_nyq = ws + plan.off_nyq;
   const int fields = e->n_members * M;
   if (!(t_events_on && t_nevents == 4)) t_events_on = false;
   err = mark(0, stream);
-  K1Args a1{e->members, data, fields, e->ny, e->nx, plan.R, plan.L, ws_main, ws_nyq, tab};
+  K1Args a1{e->members, data, fields, e->ny, e->nx, plan.R, plan.L, ws_main, tab};
   a1.n_data = K;
   if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
   if (err == hipSuccess) err = mark(1, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sweep 1 launch: %s", hipGetErrorString(err));
   K10Args a10{};
   a10.ws_main = ws_main;
-  a10.ws_nyq = ws_nyq;
   a10.R_spec = R_spec;
   for (int o = 0; o < K; ++o) a10.r_obs[o] = r_obs != nullptr ? r_obs[o] : 0.0;
   a10.N = e->n_members;
@@ -526,8 +513,7 @@ int run_observed(const fftenkf_ens* e, int M, int K, const Plan& plan, const voi
   a10.R = plan.R;
   a10.L = plan.L;
   a10.C = plan.C;
-  a10.units_main = plan.units_main;
-  a10.units_total = plan.units_total;
+  a10.units = plan.units;
   a10.group_xcd = plan.group_xcd;
   a10.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
   a10.key1 = (uint32_t)(seed >> 32);
@@ -535,7 +521,7 @@ int run_observed(const fftenkf_ens* e, int M, int K, const Plan& plan, const voi
   err = launch_k10(a10, e->dtype, stream);
   if (err == hipSuccess) err = mark(2, stream);
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "observed-block sweep launch: %s", hipGetErrorString(err));
-  K3Args a3{ws_main, ws_nyq, fields, e->ny, e->nx, plan.R, plan.L, out, tab};
+  K3Args a3{ws_main, fields, e->ny, e->nx, plan.R, plan.L, out, tab};
   err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
   if (err == hipSuccess) err = mark(3, stream);
   t_events_on = false;
@@ -670,7 +656,6 @@ int run_batch(int N, int dtype, const fftenkf_filter* fs, int n, const std::vect
         bf.R_spec = f.R_spec;
         bf.out = f.out;
         bf.ws_main = ws;
-        bf.ws_nyq = ws + plan.off_nyq;
         bf.r_scalar = f.r_scalar;
         bf.key0 = (uint32_t)(f.seed & 0xFFFFFFFFu);
         bf.key1 = (uint32_t)(f.seed >> 32);
@@ -707,13 +692,11 @@ int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
   char* ws = static_cast<char*>(e->workspace);
   void* ws_main = ws;
-  void* ws_nyq = ws + plan.off_nyq;
   const int N = e->n_members, ny = e->ny, nx = e->nx;
-  K1Args a1{e->members, data, N, ny, nx, plan.R, plan.L, ws_main, ws_nyq, tab, 1};
+  K1Args a1{e->members, data, N, ny, nx, plan.R, plan.L, ws_main, tab, 1};
   err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
   K2Args a2{};
   a2.ws_main = ws_main;
-  a2.ws_nyq = ws_nyq;
   a2.r_scalar = 1.0;
   set_k2_geometry(a2, plan, N, ny, nx, e->dtype);
   a2.chat_map = ws + plan.off_chat;
@@ -722,13 +705,13 @@ int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void
   a2.mode = K2_STATS;
   auto k2 = [&]() { return e->dtype == FFTENKF_F32 ? launch_k2_f32(a2, stream) : launch_k2_f64(a2, stream); };
   if (err == hipSuccess) err = k2();
-  K9Args a9{ws_main, ws_nyq, R_dst, e->r_scalar, N, ny, nx, plan.R, plan.L,
+  K9Args a9{ws_main, R_dst, e->r_scalar, N, ny, nx, plan.R, plan.L,
             (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), dbg_coeffs};
   if (err == hipSuccess) err = launch_dst_quad(a9, e->dtype, stream);
   if (err == hipSuccess && dbg_coeffs == nullptr) {
     a2.mode = K2_INVERSE;
     err = k2();
-    K3Args a3{ws_main, ws_nyq, N, ny, nx, plan.R, plan.L, out, tab, 1};
+    K3Args a3{ws_main, N, ny, nx, plan.R, plan.L, out, tab, 1};
     if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
   }
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sine-basis analysis launch: %s", hipGetErrorString(err));

@@ -22,7 +22,10 @@
 // formed, updated with the regenerated perturbations, inverse transformed and
 // stored.  The workspace holds member k of block j as field k M + j and d_o as
 // field N M + o; each field is addressed through its own buffer resource, so
-// any number of fields fits 32-bit offsets.
+// any number of fields fits 32-bit offsets.  The packed kx = 0 column of a fold
+// unit is split after each forward transform and joined before each inverse
+// one (spectral_unit.hpp); a pair slot's real and imaginary parts are two real
+// bins with their own statistics, gains and noise scales.
 #pragma once
 
 #include "k2_spectral.hpp"
@@ -34,8 +37,16 @@ namespace fftenkf {
 template <typename T, int NMAX, int KMAX>
 constexpr int k10_waves() { return (KMAX + 1) * NMAX * (int)sizeof(T) <= 80 ? 2 : 1; }
 
-template <typename T, int L, int NMAX, int KMAX>
-__global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) void k10_observed(const K10Args a) {
+// Two exchange buffers of two fields, W_L^k (k < L), the two fold exchange
+// buffers of two fields.
+template <typename T, int L>
+constexpr size_t k10_lds_bytes() {
+  return (2 * 2 * (size_t)K2Geom<T>::template seqp<L>() + L + 2 * 2 * (size_t)L) * sizeof(V2<T>);
+}
+
+// The work of one block (unit `unit`); FOLD as for the single-block sweep.
+template <typename T, int L, int NMAX, int KMAX, bool FOLD = true>
+__device__ __forceinline__ void k10_body(const K10Args& a, int unit) {
   constexpr int P = k2_points(L);
   constexpr int TF2 = L / P;
   constexpr int FB = 2;  // fields per LDS round
@@ -51,10 +62,10 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
   const int t2 = tid / C;
   const int N = a.N, M = a.M, K = a.K, R = a.R, ny = a.ny;
   const int nxh = a.nx >> 1, nh = nxh + 1;
-  const SpectralUnit<T> g = spectral_unit<T>(a.ws_main, a.ws_nyq, blockIdx.x, c, C, C, R, L, ny, nxh, a.units_main,
-                                             a.units_total, a.group_xcd);
+  const SpectralUnit<T> g = spectral_unit<T>(unit, c, C, R, L, ny, nxh, a.group_xcd);
   const int k2 = g.k2, kx = g.kx;
-  V2<T>* const region = static_cast<V2<T>*>(g.nyq ? a.ws_nyq : a.ws_main);
+  const bool xlane = g.fold && g.col0;
+  V2<T>* const region = static_cast<V2<T>*>(a.ws_main);
   const uint32_t fbytes = g.fstride * (uint32_t)sizeof(V2<T>);
   uint32_t voff[P];
 #pragma unroll
@@ -62,6 +73,8 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
   V2<T>* lds0 = reinterpret_cast<V2<T>*>(k10_lds_raw);
   LdsPair lp{lds0, lds0 + FB * SEQP, 0, c};
   const V2<T>* const tw = copy_twiddles<T, L>(lds0 + 2 * FB * SEQP, tab);
+  V2<T>* const xch = lds0 + 2 * FB * SEQP + L;  // two buffers of FB x L, used in turn
+  int xpar = 0;
 
   // field f through a buffer resource of its own (uniform base, 32-bit offsets)
   auto field_buf = [&](int f) __attribute__((always_inline)) -> Buf { return make_buf(region + (size_t)f * g.fstride, fbytes); };
@@ -88,6 +101,7 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
 #pragma unroll
           for (int i = 0; i < P; ++i) blk[b][i] = v[f0 + b][i];
         fft_forward<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+        if (FOLD && g.fold) fold_exchange<T, FB, FB, P, TF2, L>(blk, xch, xpar, t2, xlane, k2, true);
 #pragma unroll
         for (int b = 0; b < FB; ++b)
 #pragma unroll
@@ -97,16 +111,15 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
   };
   // inverse transforms of one LDS round and the stores of block j
   auto inverse_store = [&](int j, int f0, cx<T> (&blk)[FB][P]) __attribute__((always_inline)) {
+    if (FOLD && g.fold) fold_exchange<T, FB, FB, P, TF2, L>(blk, xch, xpar, t2, xlane, k2, false);
     fft_inverse<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
-    if (g.valid) {
 #pragma unroll
-      for (int b = 0; b < FB; ++b)
-        if (f0 + b < N) {
-          const Buf bf = field_buf((f0 + b) * M + j);
+    for (int b = 0; b < FB; ++b)
+      if (f0 + b < N) {
+        const Buf bf = field_buf((f0 + b) * M + j);
 #pragma unroll
-          for (int i = 0; i < P; ++i) buf_st(bf, voff[i], 0u, to2<T>(blk[b][i]));
-        }
-    }
+        for (int i = 0; i < P; ++i) buf_st(bf, voff[i], 0u, to2<T>(blk[b][i]));
+      }
   };
 
   const T n_tot = T(a.nx) * T(ny);
@@ -116,22 +129,33 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
   const T* __restrict__ Rspec = static_cast<const T*>(a.R_spec);
   const size_t plane = (size_t)ny * nh;
 
+  // the bins of the thread's points: point i holds bin (bky(i), bkx(i)); a pair
+  // slot only ever at points 0 and P/2
+  const ColumnBins cb = column_bins(k2, kx, t2, R, L);
+  const int kxt = cb.thr < 0 ? nxh : kx;  // outside a packed column, every point's kx
+  auto bky = [&](int i) __attribute__((always_inline)) { return cb.kyb + R * (t2 + TF2 * i); };
+  auto bkx = [&](int i) __attribute__((always_inline)) { return FOLD ? (t2 + TF2 * i > cb.thr ? nxh : kx) : kxt; };
+  auto pr = [&](int i) __attribute__((always_inline)) {
+    return FOLD && (i == 0 ? cb.pair0 : (i == P / 2 ? cb.pairh : false));
+  };
+
   // e of members 2p and 2p + 1 for observed field o at point i (the bin's
   // counter word and scales are recomputed here rather than held in registers)
-  auto draw = [&](int o, int p, int i, T amp_o, cx<T>& e0, cx<T>& e1) __attribute__((always_inline)) {
-    const BinNoise<T> bn = bin_noise<T>(kx, k2 + R * (t2 + TF2 * i), nxh, ny);
+  auto draw = [&](int o, int p, int i, T amp_o, T amp_oi, cx<T>& e0, cx<T>& e1) __attribute__((always_inline)) {
+    BinNoise<T> bn = bin_noise<T>(bkx(i), bky(i), nxh, ny);
+    if (pr(i)) bn.zi = T(1);
     const u32x4 w = philox4x32_10(u32x4{bn.ctr0, (uint32_t)p, 0u, (uint32_t)o}, a.key0, a.key1);
     T rho, cs, sn;
     box_muller_parts<T>(w.x0, w.x1, rho, cs, sn);
-    e0 = cx<T>{amp_o * bn.zs * (rho * cs), amp_o * bn.zi * (rho * sn)};
+    e0 = cx<T>{amp_o * bn.zs * (rho * cs), amp_oi * bn.zi * (rho * sn)};
     box_muller_parts<T>(w.x2, w.x3, rho, cs, sn);
-    e1 = cx<T>{amp_o * bn.zs * (rho * cs), amp_o * bn.zi * (rho * sn)};
+    e1 = cx<T>{amp_o * bn.zs * (rho * cs), amp_oi * bn.zi * (rho * sn)};
   };
 
   // ---- observed blocks: deviations, eq. (2), their own update of eq. (3)
   cx<T> del[KMAX][NMAX][P];
   cx<T> dm[KMAX][P];
-  T den[KMAX][P], amp[KMAX][P];
+  T den[KMAX][P], amp[KMAX][P], deni[KMAX][P], ampi[KMAX][P];  // the ..i: a pair slot's imaginary part
   static_for<0, KMAX>([&](auto O) __attribute__((always_inline)) {
     constexpr int o = decltype(O)::value;
     if (o < K) {
@@ -143,11 +167,12 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
         for (int i = 0; i < P; ++i) d1[0][i] = from2<T>(buf_ld<T>(b, voff[i], 0u));
         forward(del[o]);
         fft_forward<T, L, P, 1, SEQP, false, Lay, L>(d1, t2, lp, C, tw);
+        if (FOLD && g.fold) fold_exchange<T, 1, FB, P, TF2, L>(d1, xch, xpar, t2, xlane, k2, true);
 #pragma unroll
         for (int i = 0; i < P; ++i) dm[o][i] = d1[0][i];
       }
       cx<T> mean[P];
-      T gain[P];
+      T gain[P], gaini[P];
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         // deviations formed from u_k - u_0 (exactly zero for a collapsed block)
@@ -161,21 +186,33 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
           }
         del[o][0][i] = cx<T>{T(0), T(0)};
         ms = scale(ms, invN);
-        T var = T(0);
+        T vr = T(0), vi = T(0);
 #pragma unroll
         for (int k = 0; k < NMAX; ++k)
           if (k < N) {
             del[o][k][i] = del[o][k][i] - ms;
-            var += del[o][k][i].re * del[o][k][i].re + del[o][k][i].im * del[o][k][i].im;
+            vr += del[o][k][i].re * del[o][k][i].re;
+            vi += del[o][k][i].im * del[o][k][i].im;
           }
         mean[i] = u0 + ms;
         dm[o][i] = dm[o][i] - mean[i];
-        const T coo = var * var_scale;
-        T rb = T(a.r_obs[o]);
-        if (Rspec != nullptr && g.valid) rb = Rspec[(size_t)o * plane + (size_t)(k2 + R * (t2 + TF2 * i)) * nh + kx];
+        T coo = (vr + vi) * var_scale, cooi = coo;
+        if (pr(i)) {
+          coo = vr * var_scale;
+          cooi = vi * var_scale;
+        }
+        T rb = T(a.r_obs[o]), rbi = rb;
+        if (Rspec != nullptr) {
+          const T* Ro = Rspec + (size_t)o * plane + (size_t)bky(i) * nh;
+          rb = Ro[bkx(i)];
+          rbi = pr(i) ? Ro[nxh] : rb;
+        }
         den[o][i] = coo + rb;
+        deni[o][i] = pr(i) ? cooi + rbi : den[o][i];
         gain[i] = den[o][i] < tiny_normal<T>() ? T(0) : coo / den[o][i];
+        gaini[i] = pr(i) ? (deni[o][i] < tiny_normal<T>() ? T(0) : cooi / deni[o][i]) : gain[i];
         amp[o][i] = sqrt_n * sqrt_t<T>(rb);  // sqrt(n R_o)
+        ampi[o][i] = pr(i) ? sqrt_n * sqrt_t<T>(rbi) : amp[o][i];
       }
       // the observed block's update: u + g (d - mean + e - delta), per LDS round
 #pragma unroll
@@ -185,9 +222,10 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
 #pragma unroll
           for (int i = 0; i < P; ++i) {
             cx<T> e0, e1;
-            draw(o, f0 / 2, i, amp[o][i], e0, e1);
-            blk[0][i] = mean[i] + del[o][f0][i] + scale(dm[o][i] + e0 - del[o][f0][i], gain[i]);
-            blk[1][i] = mean[i] + del[o][f0 + 1][i] + scale(dm[o][i] + e1 - del[o][f0 + 1][i], gain[i]);
+            draw(o, f0 / 2, i, amp[o][i], ampi[o][i], e0, e1);
+            const cx<T> x0 = dm[o][i] + e0 - del[o][f0][i], x1 = dm[o][i] + e1 - del[o][f0 + 1][i];
+            blk[0][i] = mean[i] + del[o][f0][i] + cx<T>{x0.re * gain[i], x0.im * gaini[i]};
+            blk[1][i] = mean[i] + del[o][f0 + 1][i] + cx<T>{x1.re * gain[i], x1.im * gaini[i]};
           }
           inverse_store(o, f0, blk);
         }
@@ -202,7 +240,7 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
     cx<T> v[NMAX][P];
     load_block(j, v);
     forward(v);
-    cx<T> G[KMAX][P];
+    cx<T> G[KMAX][P];  // for a pair slot: the gains of its real and imaginary parts
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       // block j centred: its members relative to member 0, minus their mean
@@ -214,15 +252,27 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
       vm = scale(vm, invN);
       static_for<0, KMAX>([&](auto O) __attribute__((always_inline)) {
         constexpr int o = decltype(O)::value;
-        cx<T> s{T(0), T(0)};
+        // sum_k x_k conj(y_k) by its four real products: (rr + ii, ir - ri) for
+        // a bin, (rr, ii) for a pair slot's two real bins
+        T rr = T(0), ii = T(0), ir = T(0), ri = T(0);
         if (o < K) {
 #pragma unroll
           for (int k = 0; k < NMAX; ++k)
-            if (k < N) s = s + ((v[k][i] - v0) - vm) * conj(del[o][k][i]);
+            if (k < N) {
+              const cx<T> x = (v[k][i] - v0) - vm, y = del[o][k][i];
+              rr += x.re * y.re;
+              ii += x.im * y.im;
+              ir += x.im * y.re;
+              ri += x.re * y.im;
+            }
         }
-        const cx<T> cj = scale(s, var_scale);
+        const cx<T> cj = pr(i) ? cx<T>{rr * var_scale, ii * var_scale}
+                               : cx<T>{(rr + ii) * var_scale, (ir - ri) * var_scale};
         const bool none = !(o < K) || den[o][i] < tiny_normal<T>();
-        G[o][i] = none ? cx<T>{T(0), T(0)} : cx<T>{cj.re / den[o][i], cj.im / den[o][i]};
+        const bool nonei = !(o < K) || deni[o][i] < tiny_normal<T>();
+        const T gre = none ? T(0) : cj.re / den[o][i];
+        G[o][i] = pr(i) ? cx<T>{gre, nonei ? T(0) : cj.im / deni[o][i]}
+                        : cx<T>{gre, none ? T(0) : cj.im / den[o][i]};
       });
     }
 #pragma unroll
@@ -237,9 +287,15 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
             constexpr int o = decltype(O)::value;
             if (o < K) {
               cx<T> e0, e1;
-              draw(o, f0 / 2, i, amp[o][i], e0, e1);
-              blk[0][i] = blk[0][i] + G[o][i] * (dm[o][i] + e0 - del[o][f0][i]);
-              blk[1][i] = blk[1][i] + G[o][i] * (dm[o][i] + e1 - del[o][f0 + 1][i]);
+              draw(o, f0 / 2, i, amp[o][i], ampi[o][i], e0, e1);
+              const cx<T> x0 = dm[o][i] + e0 - del[o][f0][i], x1 = dm[o][i] + e1 - del[o][f0 + 1][i];
+              if (pr(i)) {  // two real bins: each part by its own gain
+                blk[0][i] = blk[0][i] + cx<T>{G[o][i].re * x0.re, G[o][i].im * x0.im};
+                blk[1][i] = blk[1][i] + cx<T>{G[o][i].re * x1.re, G[o][i].im * x1.im};
+              } else {
+                blk[0][i] = blk[0][i] + G[o][i] * x0;
+                blk[1][i] = blk[1][i] + G[o][i] * x1;
+              }
             }
           });
         }
@@ -250,10 +306,18 @@ __global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) vo
 }
 
 template <typename T, int L, int NMAX, int KMAX>
+__global__ __launch_bounds__(k2_threads_target, (k10_waves<T, NMAX, KMAX>())) void k10_observed(const K10Args a) {
+  if (unit_folds(blockIdx.x, a.C, a.R, a.nx >> 1, a.group_xcd))
+    k10_body<T, L, NMAX, KMAX, true>(a, blockIdx.x);
+  else
+    k10_body<T, L, NMAX, KMAX, false>(a, blockIdx.x);
+}
+
+template <typename T, int L, int NMAX, int KMAX>
 hipError_t launch_k10_shape(const K10Args& a, hipStream_t st) {
   constexpr int P = k2_points(L);
-  const dim3 grid(a.units_total), block(a.C * (L / P));
-  constexpr size_t lds_bytes = (2 * 2 * (size_t)K2Geom<T>::template seqp<L>() + L) * sizeof(V2<T>);
+  const dim3 grid(a.units), block(a.C * (L / P));
+  constexpr size_t lds_bytes = k10_lds_bytes<T, L>();
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k10_observed<T, L, NMAX, KMAX>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (attr != hipSuccess) return attr;

@@ -8,7 +8,10 @@
 // Their length-nx FFTs give every output: for 0 < j < R/2,
 //   A[j](kx)   = W_ny^(y1 j)     * S_j^(kx)            (0 <= kx <= nx/2)
 //   A[R-j](kx) = W_ny^(y1 (R-j)) * conj(S_j^(nx - kx))  (V_{R-j} = conj(V_j))
-// and S_0^ is split into V_0^ and V_{R/2}^ by Hermitian symmetry.
+// and S_0^ is split into V_0^ and V_{R/2}^ by Hermitian symmetry.  The kx = 0
+// and kx = nx/2 outputs are written folded (spectral_unit.hpp): row j < R/2
+// keeps A[j](0) in column 0, row R - j takes A[j](nx/2) there, and rows 0 and
+// R/2 take A[j](0) + i A[j](nx/2).
 #pragma once
 
 #include "fft_core.hpp"
@@ -30,8 +33,8 @@ struct K1Geom {
 // thread's x position j2 reads x(2 j2) for j2 < NX/2, -x(2 (NX - 1 - j2) + 1) above.
 template <typename T, int NX, int R, int SB, bool SINE>
 __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* __restrict__ data, int N, int ny,
-                                        int L, V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq,
-                                        const V2<T>* __restrict__ tab, unsigned block, int n_data = 1) {
+                                        int L, V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ tab,
+                                        unsigned block, int n_data = 1) {
   using Geo = K1Geom<T, NX>;
   constexpr int P = Geo::P, TF = Geo::TF, G = Geo::G;
   constexpr int H = R / 2;
@@ -107,9 +110,9 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
   }
 
   const size_t frow = (size_t)f * R;
-  V2<T>* __restrict__ nyq = ws_nyq + ((size_t)f * L + y1) * R;
 
-  // 4. sequences 0 < j < R/2 give rows j and R - j directly
+  // 4. sequences 0 < j < R/2 give rows j and R - j directly; column 0 of row
+  // R - j takes A[j](nx/2) (m = nx/2 is this thread's point P/2 when t = 0)
 #pragma unroll
   for (int j = 1; j < H; ++j) {
     const cx<T> wj = twiddle<T>(tab, y1 * j, ny);
@@ -123,11 +126,8 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
         const cx<T> val = s[j][i];
         if (i < P / 2) {
           rowj[m] = to2<T>(wj * val);
-          if (m == 0) rowc[0] = to2<T>(wc * conj(val));
-        } else if (m == NXH) {
-          nyq[j] = to2<T>(wj * val);
-          nyq[R - j] = to2<T>(wc * conj(val));
-        } else {
+          if (m == 0) rowc[0] = to2<T>(wj * s[j][P / 2]);
+        } else if (m != NXH) {
           rowc[NX - m] = to2<T>(wc * conj(val));
         }
       }
@@ -143,21 +143,20 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
     V2<T>* __restrict__ row0 = ws_main + ((frow + 0) * L + y1) * NXH;
     V2<T>* __restrict__ rowh = ws_main + ((frow + H) * L + y1) * NXH;
 #pragma unroll
-    for (int i = 0; i <= P / 2; ++i) {
-      // i < P/2 covers m in [0, NX/2); thread 0 also takes m = NX/2
-      if (i == P / 2 && t != 0) continue;
-      const int m = (i == P / 2) ? NXH : t + TF * i;
+    for (int i = 0; i < P / 2; ++i) {
+      const int m = t + TF * i;
       const cx<T> z = from2<T>(my[lds_pad(m)]);
       const cx<T> zc = conj(from2<T>(my[lds_pad((NX - m) & (NX - 1))]));
-      const cx<T> v0 = scale(z + zc, T(0.5));
-      const cx<T> vh = wh * scale(mul_mi(z - zc), T(0.5));
-      if (m < NXH) {
-        row0[m] = to2<T>(v0);
-        rowh[m] = to2<T>(vh);
-      } else {
-        nyq[0] = to2<T>(v0);
-        nyq[H] = to2<T>(vh);
+      cx<T> v0 = scale(z + zc, T(0.5));
+      cx<T> vh = scale(mul_mi(z - zc), T(0.5));
+      if (m == 0) {
+        // real V_0^ and V_{R/2}^ at m = 0 and m = nx/2, packed
+        const cx<T> zn = from2<T>(my[lds_pad(NXH)]);
+        v0 = cx<T>{z.re, zn.re};
+        vh = cx<T>{z.im, zn.im};
       }
+      row0[m] = to2<T>(v0);
+      rowh[m] = to2<T>(wh * vh);
     }
   }
 }
@@ -165,8 +164,8 @@ __device__ __forceinline__ void k1_body(const T* __restrict__ members, const T* 
 template <typename T, int NX, int R, int SB, bool SINE>
 __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward(
     const T* __restrict__ members, const T* __restrict__ data, int N, int ny, int L,
-    V2<T>* __restrict__ ws_main, V2<T>* __restrict__ ws_nyq, const V2<T>* __restrict__ tab, int n_data) {
-  k1_body<T, NX, R, SB, SINE>(members, data, N, ny, L, ws_main, ws_nyq, tab, blockIdx.x, n_data);
+    V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ tab, int n_data) {
+  k1_body<T, NX, R, SB, SINE>(members, data, N, ny, L, ws_main, tab, blockIdx.x, n_data);
 }
 
 // A batch of analyses on one grid: blockIdx.y selects the analysis.
@@ -174,8 +173,7 @@ template <typename T, int NX, int R, int SB>
 __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k1_forward_batch(const BatchArgs b) {
   const BatchFilter& f = b.f[blockIdx.y];
   k1_body<T, NX, R, SB, false>(static_cast<const T*>(f.members), static_cast<const T*>(f.data), b.N, b.ny, b.L,
-                        static_cast<V2<T>*>(f.ws_main), static_cast<V2<T>*>(f.ws_nyq),
-                        static_cast<const V2<T>*>(b.tab), blockIdx.x);
+                        static_cast<V2<T>*>(f.ws_main), static_cast<const V2<T>*>(b.tab), blockIdx.x);
 }
 
 template <typename T, int NX, int R>
@@ -204,11 +202,11 @@ hipError_t launch_k1_shape(const K1Args& a, hipStream_t st) {
   if (a.sine)
     hipLaunchKernelGGL((k1_forward<T, NX, R, SB, true>), grid, block, 0, st, static_cast<const T*>(a.members),
                        static_cast<const T*>(a.data), a.N, a.ny, a.L, static_cast<V2<T>*>(a.ws_main),
-                       static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab), a.n_data);
+                       static_cast<const V2<T>*>(a.tab), a.n_data);
   else
     hipLaunchKernelGGL((k1_forward<T, NX, R, SB, false>), grid, block, 0, st, static_cast<const T*>(a.members),
                        static_cast<const T*>(a.data), a.N, a.ny, a.L, static_cast<V2<T>*>(a.ws_main),
-                       static_cast<V2<T>*>(a.ws_nyq), static_cast<const V2<T>*>(a.tab), a.n_data);
+                       static_cast<const V2<T>*>(a.tab), a.n_data);
   return hipGetLastError();
 }
 

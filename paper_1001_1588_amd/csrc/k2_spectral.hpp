@@ -14,7 +14,9 @@
 // synchronisation each); every field's loads are issued before any transform,
 // and each inverse round first draws and applies its members' update.
 //
-// The unit geometry (main and Nyquist units, XCD grouping) is spectral_unit.hpp.
+// The unit geometry (XCD grouping) and the folded kx = 0 column, whose packed
+// rows a fold unit splits after its forward transforms and joins before its
+// inverse ones, are spectral_unit.hpp.
 #pragma once
 
 #include <float.h>
@@ -49,9 +51,12 @@ struct K2Geom {
   using Layout = SwizzleLayout<cols<L>(), (int)sizeof(V2<T>)>;
   template <int L>
   static constexpr int seqp() { return Layout<L>::elems(L); }
-  // two exchange buffers of fb() fields, then the block's copy of W_L^k (k < L)
+  // two exchange buffers of fb() fields, the block's copy of W_L^k (k < L), then
+  // the two fold exchange buffers of fb() fields
   template <int L, int NMAX>
-  static constexpr size_t lds_bytes() { return (2 * (size_t)fb<NMAX>() * seqp<L>() + L) * sizeof(V2<T>); }
+  static constexpr size_t lds_bytes() {
+    return (2 * (size_t)fb<NMAX>() * seqp<L>() + L + 2 * (size_t)fb<NMAX>() * L) * sizeof(V2<T>);
+  }
 };
 
 // The block's LDS copy of the twiddles W_L^k, k < L, of its length-L transforms.
@@ -89,33 +94,45 @@ __device__ __forceinline__ BinNoise<T> bin_noise(int kx, int ky, int nxh, int ny
 }
 
 // Eq. (2) at point i of a thread: the sample variance of the N members'
-// unnormalised coefficients times var_scale = 1 / ((N - 1) n).  The deviations
-// are formed from s_f = u_f - u_0 (member 0 has s_0 = 0), which leaves them
-// unchanged in exact arithmetic and makes the variance exactly zero when every
-// member is the same, so the gain guard sees a collapsed ensemble as one.
+// unnormalised coefficients times var_scale = 1 / ((N - 1) n), as the sums over
+// the real and the imaginary parts (their total for a bin; the two variances of
+// a pair slot's real bins).  The deviations are formed from s_f = u_f - u_0
+// (member 0 has s_0 = 0), which leaves them unchanged in exact arithmetic and
+// makes the variance exactly zero when every member is the same, so the gain
+// guard sees a collapsed ensemble as one.
 template <typename T, int NMAX, int P>
-__device__ __forceinline__ T sample_variance(const cx<T> (&u)[NMAX][P], int i, int N, T invN, T var_scale) {
+__device__ __forceinline__ cx<T> sample_variance(const cx<T> (&u)[NMAX][P], int i, int N, T invN, T var_scale) {
   const cx<T> u0 = u[0][i];
   cx<T> mean{T(0), T(0)};
 #pragma unroll
   for (int f = 1; f < NMAX; ++f)
     if (f < N) mean = mean + (u[f][i] - u0);
   mean = scale(mean, invN);
-  T var = mean.re * mean.re + mean.im * mean.im;  // member 0: deviation -mean
+  T vr = mean.re * mean.re, vi = mean.im * mean.im;  // member 0: deviation -mean
 #pragma unroll
   for (int f = 1; f < NMAX; ++f)
     if (f < N) {
       const cx<T> d = (u[f][i] - u0) - mean;
-      var += d.re * d.re + d.im * d.im;
+      vr += d.re * d.re;
+      vi += d.im * d.im;
     }
-  return var * var_scale;
+  return cx<T>{vr * var_scale, vi * var_scale};
 }
 
-// SPLIT compiles every mode but K2_ANALYZE (the statistics-only, inverse-only
-// and test-export modes); the single-pass variant is compiled without them.
-// The work of one block; `unit` is its index within one analysis.
-template <typename T, int L, int NMAX, bool SPLIT>
+// Kernel variants: K2V_PLAIN runs K2_ANALYZE without a given spectrum,
+// K2V_LAM K2_ANALYZE with one (lam_map), K2V_SPLIT every other mode (the
+// statistics-only, inverse-only and test-export modes); the analysis kernel
+// carries none of the others' code.
+enum { K2V_PLAIN = 0, K2V_LAM = 1, K2V_SPLIT = 2 };
+
+// The work of one block; `unit` is its index within one analysis.  FOLD:
+// carry the split and join of packed rows and the pair slots (needed only by
+// the units with g.fold); the analysis kernels run the body without them in
+// every other unit, which keeps its registers to the common case.
+template <typename T, int L, int NMAX, int VAR, bool FOLD = true>
 __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
+  constexpr bool SPLIT = VAR == K2V_SPLIT;
+  const void* const lam_map = VAR == K2V_PLAIN ? nullptr : a.lam_map;
   constexpr int P = k2_points(L);
   constexpr int TF2 = L / P;
   constexpr int FB = K2Geom<T>::template fb<NMAX>();
@@ -136,11 +153,10 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   // unit geometry; every field is read and written through one buffer
   // resource over the unit's region, with per-thread byte offsets of the P
   // elements (shared by all fields) and a uniform byte offset per field
-  const SpectralUnit<T> g = spectral_unit<T>(a.ws_main, a.ws_nyq, unit, c, C, a.Cn, R, L, ny, nxh, a.units_main,
-                                             a.units_total, a.group_xcd);
+  const SpectralUnit<T> g = spectral_unit<T>(unit, c, C, R, L, ny, nxh, a.group_xcd);
   const int k2 = g.k2, kx = g.kx;
-  const bool valid = g.valid;
-  const Buf buf = make_buf(g.nyq ? a.ws_nyq : a.ws_main, g.nyq ? a.nyq_bytes : a.main_bytes);
+  const bool xlane = g.fold && g.col0;  // a thread of a packed column
+  const Buf buf = make_buf(a.ws_main, a.main_bytes);
   const uint32_t fbytes = g.fstride * (uint32_t)sizeof(V2<T>);
   uint32_t voff[P];
 #pragma unroll
@@ -149,6 +165,8 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   LdsPair lp{lds0, lds0 + FB * SEQP, 0, c};
   // the twiddles (visible to all threads after the first exchange's barrier)
   const V2<T>* const tw = copy_twiddles<T, L>(lds0 + 2 * FB * SEQP, tab);
+  V2<T>* const xch = lds0 + 2 * FB * SEQP + L;  // two buffers of FB x L, used in turn
+  int xpar = 0;
 
   // load: members into u, data into dv (first-pass layout)
   cx<T> u[NMAX][P];
@@ -177,6 +195,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
 #pragma unroll
           for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
         fft_forward<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+        if (FOLD && g.fold) fold_exchange<T, FB, FB, P, TF2, L>(blk, xch, xpar, t2, xlane, k2, true);
 #pragma unroll
         for (int b = 0; b < FB; ++b)
 #pragma unroll
@@ -184,66 +203,128 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
       }
     }
     fft_forward<T, L, P, 1, SEQP, false, Lay, L>(dv, t2, lp, C, tw);
+    if (FOLD && g.fold) fold_exchange<T, 1, FB, P, TF2, L>(dv, xch, xpar, t2, xlane, k2, true);
   }
 
   // ---- eq. (2) per bin, then the gain g of eq. (3).  The update of a member
   // at a bin, u + g (d + e - u) with e = sqrt(n R) (zs rho cos, zi rho sin), is
   // evaluated as u (1 - g) + g d + rho (g sqrt(n R) zs cos, g sqrt(n R) zi sin):
   // the bin's factors omg = 1 - g, gd = g d and ga_re, ga_im are formed once.
+  // A pair slot (only ever at points 0 and P/2 of a thread) holds two real
+  // bins: its real and imaginary parts take their own variance, R, gain and
+  // scale (the noise then draws a for the kx = 0 bin and b for kx = nx/2,
+  // the shared draw of the two self-conjugate bins of a row).
   const T n_tot = T(a.nx) * T(ny);
   const T invN = T(1) / T(N);
   const T var_scale = T(1) / (T(N - 1) * n_tot);  // unitary (eigenvalue) scale
   const T sqrt_n = sqrt_t<T>(n_tot);
   const T* __restrict__ Rspec = static_cast<const T*>(a.R_spec);
-  T gain[P], amp_re[P], amp_im[P], omg[P], ga_re[P], ga_im[P];
+  T omg[P], omgi[P], ga_re[P], ga_im[P];
   cx<T> gd[P];
   uint32_t ctr0[P];
-  int ky[P];
+  const ColumnBins cb = column_bins(k2, kx, t2, R, L);
+  const int kxt = cb.thr < 0 ? nxh : kx;  // outside a packed column, every point's kx
   T csum = T(0);
 #pragma unroll
   for (int i = 0; i < P; ++i) {
-    ky[i] = k2 + R * (t2 + TF2 * i);
-    T chat = sample_variance<T, NMAX, P>(u, i, N, invN, var_scale);
-    if (a.lam_map != nullptr && valid) chat = static_cast<const T*>(a.lam_map)[(size_t)ky[i] * nh + kx];
-    T rb = T(a.r_scalar);
-    if (Rspec != nullptr && valid) rb = Rspec[(size_t)ky[i] * nh + kx];
-    const T den = chat + rb;
-    gain[i] = den < tiny_normal<T>() ? T(0) : chat / den;
-    const BinNoise<T> bn = bin_noise<T>(kx, ky[i], nxh, ny);
+    const int r = t2 + TF2 * i;
+    const int ky = cb.kyb + R * r, kxb = FOLD ? (r > cb.thr ? nxh : kx) : kxt;
+    const bool pr = FOLD && (i == 0 ? cb.pair0 : (i == P / 2 ? cb.pairh : false));
+    const size_t bin = (size_t)ky * nh + kxb, bin_n = (size_t)ky * nh + nxh;
+    const cx<T> vv = sample_variance<T, NMAX, P>(u, i, N, invN, var_scale);
+    T chat = vv.re + vv.im, chat_i = chat;
+    if (pr) {
+      chat = vv.re;
+      chat_i = vv.im;
+    }
+    if (lam_map != nullptr) {
+      const T* lam = static_cast<const T*>(lam_map);
+      chat = lam[bin];
+      chat_i = pr ? lam[bin_n] : chat;
+    }
+    T rb = T(a.r_scalar), rbi = rb;
+    if (Rspec != nullptr) {
+      rb = Rspec[bin];
+      rbi = pr ? Rspec[bin_n] : rb;
+    }
+    const T den = chat + rb, deni = chat_i + rbi;
+    T gain = den < tiny_normal<T>() ? T(0) : chat / den;
+    if (lam_map != nullptr && g.col0 && !pr) {
+      // a given spectrum need not be even in ky: a kx = 0 or nx/2 slot stands
+      // for its bin and the mirror (ny - ky, kx), and takes the mean of their
+      // two gains, as the c2r transform of the updated half spectrum does
+      const T cm = static_cast<const T*>(lam_map)[(size_t)((ny - ky) & (ny - 1)) * nh + kxb];
+      const T dm = cm + rb;
+      gain = T(0.5) * (gain + (dm < tiny_normal<T>() ? T(0) : cm / dm));
+    }
+    const T gain_i = pr ? (deni < tiny_normal<T>() ? T(0) : chat_i / deni) : gain;
+    BinNoise<T> bn = bin_noise<T>(kxb, ky, nxh, ny);
+    if (pr) bn.zi = T(1);
     const T amp = sqrt_n * sqrt_t<T>(rb);  // sqrt(n R), without overflow of n R
-    amp_re[i] = amp * bn.zs;
-    amp_im[i] = amp * bn.zi;
+    const T amp_i = pr ? sqrt_n * sqrt_t<T>(rbi) : amp;
+    const T amp_re = amp * bn.zs, amp_im = amp_i * bn.zi;
     ctr0[i] = bn.ctr0;
-    omg[i] = T(1) - gain[i];
-    gd[i] = scale(dv[0][i], gain[i]);
-    ga_re[i] = gain[i] * amp_re[i];
-    ga_im[i] = gain[i] * amp_im[i];
+    omg[i] = T(1) - gain;
+    omgi[i] = pr ? T(1) - gain_i : omg[i];
+    gd[i] = cx<T>{gain * dv[0][i].re, gain_i * dv[0][i].im};
+    ga_re[i] = gain * amp_re;
+    ga_im[i] = gain_i * amp_im;
     if constexpr (SPLIT) {
+      // exports cover the whole half spectrum: a kx = 0 column slot also writes
+      // the mirror bin (ny - ky, kx) (the conjugate), a pair slot both real bins
+      const size_t mir = (size_t)((ny - ky) & (ny - 1)) * nh + kxb;
+      auto put_real = [&](T* plane, T v, T vi) __attribute__((always_inline)) {
+        plane[bin] = v;
+        if (pr) plane[bin_n] = vi;
+        else if (g.col0) plane[mir] = v;
+      };
+      auto put_cx = [&](V2<T>* plane, cx<T> v) __attribute__((always_inline)) {
+        if (pr) {
+          plane[bin] = to2<T>(cx<T>{v.re, T(0)});
+          plane[bin_n] = to2<T>(cx<T>{v.im, T(0)});
+        } else {
+          plane[bin] = to2<T>(v);
+          if (g.col0) plane[mir] = to2<T>(conj(v));
+        }
+      };
       if (mode == K2_STATS || mode == K2_CHAT) {
-        if (valid) static_cast<T*>(a.chat_map)[(size_t)ky[i] * nh + kx] = chat;
-        csum += valid ? chat : T(0);
+        put_real(static_cast<T*>(a.chat_map), chat, chat_i);
+        csum += pr ? chat + chat_i : (g.col0 ? T(2) * chat : chat);
       }
-      if (mode == K2_DEBUG_SPECTRA && valid) {
-        const size_t bin = (size_t)ky[i] * nh + kx;
-        static_cast<T*>(a.dbg_chat)[bin] = chat;
-        static_cast<T*>(a.dbg_gain)[bin] = gain[i];
+      if (mode == K2_DEBUG_SPECTRA) {
+        put_real(static_cast<T*>(a.dbg_chat), chat, chat_i);
+        put_real(static_cast<T*>(a.dbg_gain), gain, gain_i);
         if (a.dbg_spec != nullptr) {
           V2<T>* sp = static_cast<V2<T>*>(a.dbg_spec);
           const T us = T(1) / sqrt_n;
           const size_t plane = (size_t)ny * nh;
 #pragma unroll
           for (int f = 0; f < NMAX; ++f)
-            if (f < N) sp[f * plane + bin] = to2<T>(scale(u[f][i], us));
-          sp[N * plane + bin] = to2<T>(scale(dv[0][i], us));
+            if (f < N) put_cx(sp + f * plane, scale(u[f][i], us));
+          put_cx(sp + N * plane, scale(dv[0][i], us));
+        }
+      }
+      if (mode == K2_DEBUG_PERTURB) {  // test export of e_hat (unitary scale)
+        V2<T>* ep = static_cast<V2<T>*>(a.dbg_e);
+        const T us = T(1) / sqrt_n;
+        const size_t plane = (size_t)ny * nh;
+        for (int p = 0; 2 * p < N; ++p) {
+          const u32x4 w = philox4x32_10(u32x4{ctr0[i], (uint32_t)p, 0u, 0u}, a.key0, a.key1);
+          T rho0, c0, s0, rho1, c1, s1;
+          box_muller_parts<T>(w.x0, w.x1, rho0, c0, s0);
+          box_muller_parts<T>(w.x2, w.x3, rho1, c1, s1);
+          put_cx(ep + (2 * p) * plane, scale(cx<T>{amp_re * (rho0 * c0), amp_im * (rho0 * s0)}, us));
+          if (2 * p + 1 < N)
+            put_cx(ep + (2 * p + 1) * plane, scale(cx<T>{amp_re * (rho1 * c1), amp_im * (rho1 * s1)}, us));
         }
       }
     }
   }
   if constexpr (SPLIT) {
-    if (mode == K2_DEBUG_SPECTRA) return;  // no synchronisation follows
+    if (mode == K2_DEBUG_SPECTRA || mode == K2_DEBUG_PERTURB) return;  // no synchronisation follows
     if (mode == K2_STATS || mode == K2_CHAT) {
       // transformed fields back in place (K2_STATS), and this block's sum of c_hat
-      if (valid && mode == K2_STATS) {
+      if (mode == K2_STATS) {
 #pragma unroll
         for (int f = 0; f < NMAX; ++f)
           if (f < N) {
@@ -279,34 +360,16 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
           T rho0, c0, s0, rho1, c1, s1;
           box_muller_parts<T>(w.x0, w.x1, rho0, c0, s0);
           box_muller_parts<T>(w.x2, w.x3, rho1, c1, s1);
-          if (SPLIT && mode == K2_DEBUG_PERTURB) {  // test export of e_hat (unitary scale)
-            if (valid) {
-              const cx<T> e0{amp_re[i] * (rho0 * c0), amp_im[i] * (rho0 * s0)};
-              const cx<T> e1{amp_re[i] * (rho1 * c1), amp_im[i] * (rho1 * s1)};
-              V2<T>* ep = static_cast<V2<T>*>(a.dbg_e);
-              const T us = T(1) / sqrt_n;
-              const size_t bin = (size_t)ky[i] * nh + kx, plane = (size_t)ny * nh;
-              ep[(2 * p) * plane + bin] = to2<T>(scale(e0, us));
-              if (2 * p + 1 < N) ep[(2 * p + 1) * plane + bin] = to2<T>(scale(e1, us));
-            }
-          } else {
-            const cx<T> ua = u[2 * p][i], ub = u[2 * p + 1][i];
-            u[2 * p][i] = cx<T>{fma_t(rho0 * ga_re[i], c0, fma_t(ua.re, omg[i], gd[i].re)),
-                                fma_t(rho0 * ga_im[i], s0, fma_t(ua.im, omg[i], gd[i].im))};
-            if (2 * p + 1 < N)
-              u[2 * p + 1][i] = cx<T>{fma_t(rho1 * ga_re[i], c1, fma_t(ub.re, omg[i], gd[i].re)),
-                                      fma_t(rho1 * ga_im[i], s1, fma_t(ub.im, omg[i], gd[i].im))};
-          }
+          const cx<T> ua = u[2 * p][i], ub = u[2 * p + 1][i];
+          u[2 * p][i] = cx<T>{fma_t(rho0 * ga_re[i], c0, fma_t(ua.re, omg[i], gd[i].re)),
+                              fma_t(rho0 * ga_im[i], s0, fma_t(ua.im, omgi[i], gd[i].im))};
+          if (2 * p + 1 < N)
+            u[2 * p + 1][i] = cx<T>{fma_t(rho1 * ga_re[i], c1, fma_t(ub.re, omg[i], gd[i].re)),
+                                    fma_t(rho1 * ga_im[i], s1, fma_t(ub.im, omgi[i], gd[i].im))};
         }
       });
     });
   };
-  if constexpr (SPLIT) {
-    if (mode == K2_DEBUG_PERTURB) {
-      perturb(std::integral_constant<int, 0>{}, std::integral_constant<int, NMAX / 2>{});
-      return;  // no synchronisation follows
-    }
-  }
 
   // ---- per LDS round: update its members (their perturbations are drawn here,
   // so the stores of one round overlap the arithmetic of the next), then the
@@ -321,8 +384,11 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
       for (int b = 0; b < FB; ++b)
 #pragma unroll
         for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
+      if (FOLD && g.fold) fold_exchange<T, FB, FB, P, TF2, L>(blk, xch, xpar, t2, xlane, k2, false);
       fft_inverse<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
-      if (valid) {
+      // kx < nx/2 always holds: the branch keeps the compiler from moving a
+      // round's stores into the next round's arithmetic, which costs registers
+      if (kx < nxh) {
 #pragma unroll
         for (int b = 0; b < FB; ++b)
           if (f0 + b < N) {
@@ -334,9 +400,24 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   });
 }
 
-template <typename T, int L, int NMAX, bool SPLIT>
+// Whether unit `unit` holds a packed column (spectral_unit's g.fold).
+__device__ __forceinline__ bool unit_folds(int unit, int C, int R, int nxh, int group_xcd) {
+  int um = unit;
+  if (group_xcd > 1) {
+    const int x = um & 7, q = um >> 3;
+    um = group_xcd * (((q / group_xcd) << 3) + x) + (q & (group_xcd - 1));
+  }
+  const int nchunk = nxh / C;
+  const int k2 = um / nchunk;
+  return um - k2 * nchunk == 0 && (k2 == 0 || k2 == (R >> 1));
+}
+
+template <typename T, int L, int NMAX, int VAR>
 __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args a) {
-  k2_body<T, L, NMAX, SPLIT>(a, blockIdx.x);
+  if (VAR == K2V_SPLIT || unit_folds(blockIdx.x, a.C, a.R, a.nx >> 1, a.group_xcd))
+    k2_body<T, L, NMAX, VAR, true>(a, blockIdx.x);
+  else
+    k2_body<T, L, NMAX, VAR, false>(a, blockIdx.x);
 }
 
 // A batch of analyses on one grid: blockIdx.y selects the analysis; b.k2 holds
@@ -346,18 +427,20 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral_batch(const 
   const BatchFilter& f = b.f[blockIdx.y];
   K2Args a = b.k2;
   a.ws_main = f.ws_main;
-  a.ws_nyq = f.ws_nyq;
   a.R_spec = f.R_spec;
   a.r_scalar = f.r_scalar;
   a.key0 = f.key0;
   a.key1 = f.key1;
-  k2_body<T, L, NMAX, false>(a, blockIdx.x);
+  if (unit_folds(blockIdx.x, a.C, a.R, a.nx >> 1, a.group_xcd))
+    k2_body<T, L, NMAX, K2V_PLAIN, true>(a, blockIdx.x);
+  else
+    k2_body<T, L, NMAX, K2V_PLAIN, false>(a, blockIdx.x);
 }
 
 template <typename T, int L, int NMAX>
 hipError_t launch_k2_batch_shape(const BatchArgs& b, hipStream_t st) {
   constexpr int P = k2_points(L);
-  const dim3 grid(b.k2.units_total, b.count), block(b.k2.C * (L / P));
+  const dim3 grid(b.k2.units, b.count), block(b.k2.C * (L / P));
   constexpr size_t lds_bytes = K2Geom<T>::template lds_bytes<L, NMAX>();
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_spectral_batch<T, L, NMAX>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
@@ -366,22 +449,23 @@ hipError_t launch_k2_batch_shape(const BatchArgs& b, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T, int L, int NMAX, bool SPLIT>
+template <typename T, int L, int NMAX, int VAR>
 hipError_t launch_k2_variant(const K2Args& a, hipStream_t st) {
   constexpr int P = k2_points(L);
-  const dim3 grid(a.units_total), block(a.C * (L / P));
+  const dim3 grid(a.units), block(a.C * (L / P));
   constexpr size_t lds_bytes = K2Geom<T>::template lds_bytes<L, NMAX>();
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_spectral<T, L, NMAX, SPLIT>),
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k2_spectral<T, L, NMAX, VAR>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k2_spectral<T, L, NMAX, SPLIT>), grid, block, lds_bytes, st, a);
+  hipLaunchKernelGGL((k2_spectral<T, L, NMAX, VAR>), grid, block, lds_bytes, st, a);
   return hipGetLastError();
 }
 
 template <typename T, int L, int NMAX>
 hipError_t launch_k2_shape(const K2Args& a, hipStream_t st) {
-  if (a.mode != K2_ANALYZE) return launch_k2_variant<T, L, NMAX, true>(a, st);
-  return launch_k2_variant<T, L, NMAX, false>(a, st);
+  if (a.mode != K2_ANALYZE) return launch_k2_variant<T, L, NMAX, K2V_SPLIT>(a, st);
+  if (a.lam_map != nullptr) return launch_k2_variant<T, L, NMAX, K2V_LAM>(a, st);
+  return launch_k2_variant<T, L, NMAX, K2V_PLAIN>(a, st);
 }
 
 }  // namespace fftenkf

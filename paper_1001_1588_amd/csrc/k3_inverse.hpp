@@ -12,7 +12,11 @@
 //   Z_j(m) = U(j, m)                           0 < m < nx/2
 //          = conj U(R-j, nx-m)                 nx/2 < m < nx
 //          = (U(j, m) + conj U(R-j, m)) / 2    m in {0, nx/2}
-// and w_0 that of H_0 + i H_{R/2}, H_j the Hermitian part of U(j, .).
+// and w_0 that of H_0 + i H_{R/2}, H_j the Hermitian part of U(j, .).  The
+// kx = 0 and kx = nx/2 entries are read from the folded column 0
+// (spectral_unit.hpp): for a real result U(R-j, m) = conj U(j, m) there, so the
+// m = 0 entry of row j is U(j, 0) and the m = nx/2 entry is the value folded
+// into row R - j; rows 0 and R/2 hold both as real and imaginary parts.
 #pragma once
 
 #include "fft_core.hpp"
@@ -25,8 +29,8 @@ namespace fftenkf {
 // SINE: row j1, x position j2 of the result goes to out(i1, i2) times
 // (-1)^(i1 + i2), i = dst_rho(j) (the converse of sweep 1's reordering).
 template <typename T, int NX, int R, int SB, bool SINE>
-__device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ ws_nyq, int N,
-                                        int ny, int L, T out_scale, T* __restrict__ out,
+__device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, int N, int ny, int L, T out_scale,
+                                        T* __restrict__ out,
                                         const V2<T>* __restrict__ tab, int block) {
   using Geo = K1Geom<T, NX>;
   constexpr int P = Geo::P, TF = Geo::TF, G = Geo::G;
@@ -45,7 +49,6 @@ __device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, const
   V2<T>* my = lds + g * SB * SEQP;
   LdsPair lp{my, nullptr, 0, 0};
   const size_t frow = (size_t)f * R;
-  const V2<T>* __restrict__ nyq = ws_nyq + ((size_t)f * L + y1) * R;
 
   // twiddle (inverse) and normalisation for row k2
   auto tw = [&](int k2) -> cx<T> { return scale(conj(twiddle<T>(tab, y1 * k2, ny)), out_scale); };
@@ -62,8 +65,8 @@ __device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, const
     const cx<T> wj = tw(j), wc = tw(R - j);
     const V2<T>* __restrict__ rj = row(j);
     const V2<T>* __restrict__ rc = row(R - j);
-    const cx<T> zero_m = scale(wj * from2<T>(rj[0]) + conj(wc * from2<T>(rc[0])), T(0.5));
-    const cx<T> nyq_m = scale(wj * from2<T>(nyq[j]) + conj(wc * from2<T>(nyq[R - j])), T(0.5));
+    const cx<T> zero_m = wj * from2<T>(rj[0]);
+    const cx<T> nyq_m = wj * from2<T>(rc[0]);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int m = t + TF * i;
@@ -82,8 +85,9 @@ __device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, const
     const cx<T> w0 = tw(0), wh = tw(H);
     const V2<T>* __restrict__ r0 = row(0);
     const V2<T>* __restrict__ rh = row(H);
-    const cx<T> zero_m{(w0 * from2<T>(r0[0])).re, (wh * from2<T>(rh[0])).re};   // H_0 + i H_{R/2} at m = 0
-    const cx<T> nyq_m{(w0 * from2<T>(nyq[0])).re, (wh * from2<T>(nyq[H])).re};  // and at m = nx/2
+    const cx<T> p0 = w0 * from2<T>(r0[0]), ph = wh * from2<T>(rh[0]);  // packed
+    const cx<T> zero_m{p0.re, ph.re};  // H_0 + i H_{R/2} at m = 0
+    const cx<T> nyq_m{p0.im, ph.im};   // and at m = nx/2
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       const int m = t + TF * i;
@@ -154,18 +158,17 @@ __device__ __forceinline__ void k3_body(const V2<T>* __restrict__ ws_main, const
 
 template <typename T, int NX, int R, int SB, bool SINE>
 __global__ __launch_bounds__((K1Geom<T, NX>::threads), (SINE ? 2 : 1)) void k3_inverse(
-    const V2<T>* __restrict__ ws_main, const V2<T>* __restrict__ ws_nyq, int N, int ny, int L, T out_scale,
-    T* __restrict__ out, const V2<T>* __restrict__ tab) {
-  k3_body<T, NX, R, SB, SINE>(ws_main, ws_nyq, N, ny, L, out_scale, out, tab, blockIdx.x);
+    const V2<T>* __restrict__ ws_main, int N, int ny, int L, T out_scale, T* __restrict__ out,
+    const V2<T>* __restrict__ tab) {
+  k3_body<T, NX, R, SB, SINE>(ws_main, N, ny, L, out_scale, out, tab, blockIdx.x);
 }
 
 // A batch of analyses on one grid: blockIdx.y selects the analysis.
 template <typename T, int NX, int R, int SB>
 __global__ __launch_bounds__((K1Geom<T, NX>::threads)) void k3_inverse_batch(const BatchArgs b) {
   const BatchFilter& f = b.f[blockIdx.y];
-  k3_body<T, NX, R, SB, false>(static_cast<const V2<T>*>(f.ws_main), static_cast<const V2<T>*>(f.ws_nyq), b.N, b.ny, b.L,
-                        T(1) / (T(b.nx) * T(b.ny)), static_cast<T*>(f.out), static_cast<const V2<T>*>(b.tab),
-                        blockIdx.x);
+  k3_body<T, NX, R, SB, false>(static_cast<const V2<T>*>(f.ws_main), b.N, b.ny, b.L, T(1) / (T(b.nx) * T(b.ny)),
+                               static_cast<T*>(f.out), static_cast<const V2<T>*>(b.tab), blockIdx.x);
 }
 
 template <typename T, int NX, int R>
@@ -186,12 +189,10 @@ hipError_t launch_k3_shape(const K3Args& a, hipStream_t st) {
   const T out_scale = T(1) / (T(a.nx) * T(a.ny));
   if (a.sine)
     hipLaunchKernelGGL((k3_inverse<T, NX, R, SB, true>), grid, block, 0, st, static_cast<const V2<T>*>(a.ws_main),
-                       static_cast<const V2<T>*>(a.ws_nyq), a.N, a.ny, a.L, out_scale, static_cast<T*>(a.out),
-                       static_cast<const V2<T>*>(a.tab));
+                       a.N, a.ny, a.L, out_scale, static_cast<T*>(a.out), static_cast<const V2<T>*>(a.tab));
   else
     hipLaunchKernelGGL((k3_inverse<T, NX, R, SB, false>), grid, block, 0, st, static_cast<const V2<T>*>(a.ws_main),
-                       static_cast<const V2<T>*>(a.ws_nyq), a.N, a.ny, a.L, out_scale, static_cast<T*>(a.out),
-                       static_cast<const V2<T>*>(a.tab));
+                       a.N, a.ny, a.L, out_scale, static_cast<T*>(a.out), static_cast<const V2<T>*>(a.tab));
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@
 #include "fft_core.hpp"
 #include "kernels.hpp"
 #include "philox.hpp"
+#include "spectral_unit.hpp"
 
 namespace fftenkf {
 
@@ -44,14 +45,28 @@ template <typename T> __device__ __forceinline__ T tiny_t();
 template <> __device__ __forceinline__ float tiny_t<float>() { return 1.17549435e-38f; }
 template <> __device__ __forceinline__ double tiny_t<double>() { return 2.2250738585072014e-308; }
 
-// Index of V(ky, kx) of field 0 in the transformed layout of sweep 2; field f
-// is f * field_stride elements further.
+// V(ky, kx) of field 0 in the transformed layout of sweep 2 (field f is f *
+// fstride elements further): its slot and how it is read (bin_slot).
 template <typename T>
-__device__ __forceinline__ V2<T>* spectrum_at(const K9Args& a, int ky, int kx) {
+struct SpecRef {
+  V2<T>* p;
+  int op;
+  __device__ __forceinline__ cx<T> load(size_t off) const {
+    const cx<T> v = from2<T>(p[off]);
+    return op == 0 ? v : op == 1 ? conj(v) : op == 2 ? cx<T>{v.re, T(0)} : cx<T>{v.im, T(0)};
+  }
+  // only the bin that owns the slot writes it (a pair slot: its own part)
+  __device__ __forceinline__ void store(size_t off, cx<T> v) const {
+    if (op == 0) p[off] = to2<T>(v);
+    else if (op == 2) reinterpret_cast<T*>(p + off)[0] = v.re;
+    else if (op == 3) reinterpret_cast<T*>(p + off)[1] = v.re;
+  }
+};
+template <typename T>
+__device__ __forceinline__ SpecRef<T> spectrum_at(const K9Args& a, int ky, int kx) {
   const int nxh = a.nx / 2;
-  const int k2 = ky % a.R, k1 = ky / a.R;
-  if (kx < nxh) return static_cast<V2<T>*>(a.ws_main) + ((size_t)k2 * a.L + k1) * nxh + kx;
-  return static_cast<V2<T>*>(a.ws_nyq) + (size_t)k1 * a.R + k2;
+  const BinSlot sl = bin_slot(ky, kx, a.R, a.L, nxh);
+  return SpecRef<T>{static_cast<V2<T>*>(a.ws_main) + ((size_t)sl.k2 * a.L + sl.k1) * nxh + sl.col, sl.op};
 }
 
 // One thread per mirror set {a, n1-a} x {b, n2-b}, 0 <= a <= n1/2, 0 <= b <= n2/2.
@@ -84,9 +99,9 @@ __global__ __launch_bounds__(256) void dst_quad(const K9Args a) {
 #pragma unroll
   for (int p = 0; p < 4; ++p) alpha[p] = (pk1[p] == 0 ? r1 : r1b) * (pk2[p] == 0 ? r2 : r2b);
   // the two stored points of every field
-  const size_t fstride = qb < n2 / 2 ? (size_t)a.R * a.L * (n2 / 2) : (size_t)a.L * a.R;
-  V2<T>* const va = spectrum_at<T>(a, qa, qb);
-  V2<T>* const vm = spectrum_at<T>(a, ma, qb);
+  const size_t fstride = (size_t)a.R * a.L * (n2 / 2);
+  const SpecRef<T> va = spectrum_at<T>(a, qa, qb);
+  const SpecRef<T> vm = spectrum_at<T>(a, ma, qb);
 
   // X of every field at the four points (member k in row k, d in row NMAX;
   // padding rows are never read)
@@ -95,8 +110,8 @@ __global__ __launch_bounds__(256) void dst_quad(const K9Args a) {
   for (int f = 0; f <= NMAX; ++f) {
     if (f < N || f == NMAX) {
       const size_t off = (size_t)(f == NMAX ? N : f) * fstride;
-      const cx<T> Vab = from2<T>(va[off]);
-      const cx<T> Vmb = from2<T>(vm[off]);
+      const cx<T> Vab = va.load(off);
+      const cx<T> Vmb = vm.load(off);
       // V at (qa, -qb) = conj V(ma, qb); at (ma, -qb) = conj V(qa, qb)
       const cx<T> Vp[4] = {Vab, Vmb, conj(Vmb), conj(Vab)};
       const cx<T> Vn[4] = {conj(Vmb), conj(Vab), Vab, Vmb};  // V at (k1, -k2) of each point
@@ -176,13 +191,13 @@ __global__ __launch_bounds__(256) void dst_quad(const K9Args a) {
     const T x_mc = qb == 0 ? T(0) : Y[2];              // X(qa, n2 - qb)
     const T x_mm = (qa == 0 || qb == 0) ? T(0) : Y[3];  // X(n1 - qa, n2 - qb)
     const size_t off = (size_t)f * fstride;
-    va[off] = to2<T>(conj(W1[0] * W2[0]) * cx<T>{x_ab - x_mm, -(x_mr + x_mc)});
+    va.store(off, conj(W1[0] * W2[0]) * cx<T>{x_ab - x_mm, -(x_mr + x_mc)});
     if (da) {
       // for the point (ma, qb): X(n1 - ma, .) = X(qa, .), never at index n
       const T y_ab = Y[1], y_mr = Y[0];
       const T y_mc = qb == 0 ? T(0) : Y[3];
       const T y_mm = qb == 0 ? T(0) : Y[2];
-      vm[off] = to2<T>(conj(W1[1] * W2[1]) * cx<T>{y_ab - y_mm, -(y_mr + y_mc)});
+      vm.store(off, conj(W1[1] * W2[1]) * cx<T>{y_ab - y_mm, -(y_mr + y_mc)});
     }
   }
 }

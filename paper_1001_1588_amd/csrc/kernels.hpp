@@ -9,10 +9,10 @@
 // the gain, the perturbations and the update, then the inverse length-L
 // transform; the third sweep (k3) undoes the first.
 //
-// Workspace (complex, dtype T):
-//   main [NF][R][L][nx/2]   element (f, k2, y1, kx) for kx < nx/2
-//   nyq  [NF][L][R]         element (f, y1, k2) for kx = nx/2 (the Nyquist column)
-// with NF = N + 1 fields (the N members, then the data d).
+// Workspace (complex, dtype T): [NF][R][L][nx/2], element (f, k2, y1, kx), with
+// NF = N + 1 fields (the N members, then the data d).  The Nyquist column
+// kx = nx/2 has no storage of its own: it is folded into column kx = 0
+// (spectral_unit.hpp).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,7 +26,6 @@ struct K1Args {
   const void* data;     // [n_data][ny][nx]: fields N .. N + n_data - 1
   int N, ny, nx, R, L;
   void* ws_main;
-  void* ws_nyq;
   const void* tab;  // W_4096^k table of dtype's complex type (device)
   int sine = 0;     // 1: transform the sine-basis reordering of the fields (dst_rho)
   int n_data = 1;   // data fields after the N member fields
@@ -54,11 +53,10 @@ enum K2Mode {
 
 struct K2Args {
   void* ws_main;
-  void* ws_nyq;
-  uint32_t main_bytes, nyq_bytes;  // sizes of the two regions (each below 2^31)
+  uint32_t main_bytes;  // size of the workspace's spectral region (below 2^31)
   const void* R_spec;  // [ny][nx/2+1] or nullptr
   double r_scalar;
-  int N, ny, nx, R, L, C, Cn, units_main, units_total;  // Cn: k2 columns of a Nyquist unit
+  int N, ny, nx, R, L, C, units;
   int group_xcd;  // G > 1: blocks b, b+8, .., b+8(G-1) take G adjacent kx chunks of one k2
   uint32_t key0, key1;
   int mode;
@@ -67,7 +65,7 @@ struct K2Args {
   void* dbg_spec;  // [N+1][ny][nx/2+1] complex, or nullptr
   void* dbg_e;     // [N][ny][nx/2+1] complex
   void* chat_map;  // [ny][nx/2+1] real (K2_STATS)
-  void* partials;  // [units_total] float (K2_STATS)
+  void* partials;  // [units] float (K2_STATS)
   const void* lam_map;  // [ny][nx/2+1] real, or nullptr
   const void* tab;
 };
@@ -78,10 +76,9 @@ struct K2Args {
 constexpr int kMaxObserved = 3;
 struct K10Args {
   void* ws_main;
-  void* ws_nyq;
   const void* R_spec;          // [K][ny][nx/2+1] or nullptr
   double r_obs[kMaxObserved];  // R_o = r_obs[o] I when R_spec is nullptr
-  int N, M, K, ny, nx, R, L, C, units_main, units_total, group_xcd;
+  int N, M, K, ny, nx, R, L, C, units, group_xcd;
   uint32_t key0, key1;
   const void* tab;
 };
@@ -95,7 +92,6 @@ struct BatchFilter {
   const void* R_spec;   // [ny][nx/2+1] or nullptr
   void* out;            // [N][ny][nx]
   void* ws_main;
-  void* ws_nyq;
   double r_scalar;
   uint32_t key0, key1;
 };
@@ -109,7 +105,6 @@ struct BatchArgs {
 
 struct K3Args {
   const void* ws_main;
-  const void* ws_nyq;
   int N, ny, nx, R, L;
   void* out;  // [N][ny][nx]
   const void* tab;
@@ -167,10 +162,11 @@ hipError_t launch_k7(const K7Args& a, hipStream_t s);
 
 // Test exports: move N half spectra ([N][ny][nx/2+1] complex, scaled by
 // `scale`) out of / into the transformed layout the spectral sweep leaves in
-// the workspace (main [f][k2][k1][kx < nx/2], nyq [f][k1][k2], ky = k2 + R k1).
+// the workspace ([f][k2][k1][kx < nx/2], ky = k2 + R k1, the kx = 0 and
+// kx = nx/2 columns folded as bin_slot describes).  The scatter writes only the
+// slot-owning bins: the kx = 0 and nx/2 bins above ny/2 are implied.
 struct K8Args {
   void* ws_main;
-  void* ws_nyq;
   int N, ny, nx, R, L;
   double scale;
   void* spectra;
@@ -182,7 +178,6 @@ hipError_t launch_k8_scatter(const K8Args& a, int dtype, hipStream_t s);
 // writes the transformed fields in the workspace layout of K2Args.
 struct K9Args {
   void* ws_main;
-  void* ws_nyq;
   const void* R_dst;  // [ny][nx] eigenvalues of R in the sine basis, or nullptr
   double r_scalar;
   int N, ny, nx, R, L;

@@ -115,12 +115,13 @@ def test_workspace_formula(built_lib):
     for (N, ny, nx, dt, s) in [(20, 2048, 2048, 0, 4), (5, 64, 64, 1, 8), (2, 8, 8, 0, 4), (24, 4096, 4096, 0, 4)]:
         nh = nx // 2 + 1
         r256 = lambda b: (b + 255) // 256 * 256  # noqa: E731
-        # spectra of the N+1 fields, then c_hat and lambda_hat planes, then one float per unit
+        # spectra of the N+1 fields (kx < nx/2: the Nyquist column is folded into
+        # kx = 0), then c_hat and lambda_hat planes, then one float per unit
         R = min(ny, (16 if nx <= 2048 else 8) if dt == 0 else (8 if nx <= 2048 else 4))
         L = ny // R
         C = min(nx // 2, 256 // (L // min(4, L)))
-        units = R * (nx // 2 // C) + (R + C - 1) // C
-        raw = r256(r256(r256((N + 1) * ny * nh * 2 * s) + ny * nh * s) + ny * nh * s) + 4 * units
+        units = R * (nx // 2 // C)
+        raw = r256(r256(r256((N + 1) * ny * (nx // 2) * 2 * s) + ny * nh * s) + ny * nh * s) + 4 * units
         assert lib.fftenkf_workspace_bytes(N, ny, nx, dt) == r256(raw)
     assert lib.fftenkf_workspace_bytes(1, 8, 8, 0) == 0
     assert lib.fftenkf_workspace_bytes(4, 8, 12, 0) == 0

@@ -5,7 +5,7 @@ the working precision there is neither spread nor data error, and the gain is
 0.  The spread of identical members is exactly zero on both sides (eq. (2) is
 summed over deviations from member 0), so these cases reach the guarded
 division itself, with R = 0 on bins that include the self-conjugate bins, the
-kx = 0 and kx = nx/2 columns and the Nyquist units of the spectral sweep:
+kx = 0 and kx = nx/2 columns (the packed column of the spectral sweep):
 
 * identical members, R zero on a subset of bins: every gain is 0 and the
   analysis returns the forecast (single block, multi-block, sine basis; the
@@ -56,7 +56,7 @@ def masked_R(ny, nx, rng, dtype):
     return R.astype(dtype)
 
 
-# (ny, nx, N, dtype): several tiles of every sweep and Nyquist units, both precisions
+# (ny, nx, N, dtype): several tiles of every sweep and packed kx = 0 rows, both precisions
 SHAPES = [(16, 16, 3, np.float32), (64, 128, 5, np.float32), (256, 64, 20, np.float32),
           (2048, 64, 7, np.float32), (32, 32, 4, np.float64), (128, 64, 8, np.float64)]
 
