@@ -35,6 +35,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+def progress(msg: str) -> None:
+    """A progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 class HipEvents:
     """Minimal hipEvent_t wrapper on the HIP runtime torch has loaded."""
 
@@ -124,10 +129,29 @@ def copy_ceiling(mib: int, hip: HipEvents, reps: int = 10) -> dict:
     return {"bytes_per_copy": 2 * (mib << 20), "ms": ms, "GBps": 2 * (mib << 20) / (ms * 1e-3) / 1e9}
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and the processor counts this process sees."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(tw, members: int) -> dict:
     from threadpoolctl import threadpool_info
 
     from oracle import enkf
+    from paper_1001_1588_amd import twin
 
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     ens = tw.ens[:members]
@@ -135,9 +159,20 @@ def cpu_baseline(tw, members: int) -> dict:
     enkf.analyze(ens, tw.data, tw.R_spec, tw.seed)
     dt = time.perf_counter() - t0
     ny, nx = tw.data.shape
+    # the small configuration as well: 64 x 64, float64, N = 5 (repeated to a measurable time)
+    sm = twin.workload("small64")
+    reps, t1 = 0, time.perf_counter()
+    while reps < 3 or time.perf_counter() - t1 < 1.0:
+        enkf.analyze(sm.ens, sm.data, sm.R_spec, sm.seed)
+        reps += 1
+    ds = (time.perf_counter() - t1) / reps
+    sN, sny, snx = sm.ens.shape
     return {"value": members * ny * nx / dt, "unit": "member-gridpoints/s", "cores": int(threads), "kind": "oracle",
             "sample": f"float64 oracle (matrix DFT, numpy/OpenBLAS) on the full {ny}x{nx} grid, "
-                      f"{members} of the {tw.ens.shape[0]} members plus d, one analysis, {dt:.1f} s"}
+                      f"{members} of the {tw.ens.shape[0]} members plus d, one analysis, {dt:.1f} s",
+            **host_cpu(),
+            "small64": {"value": sN * sny * snx / ds, "unit": "member-gridpoints/s", "ms_per_analysis": 1e3 * ds,
+                        "sample": f"{snx}x{sny}, float64, N={sN}, {reps} analyses"}}
 
 
 MLP_FLOPS_PER_BIN = 2 * (26 * 64 + 64 * 64 + 64 * 64 + 64)  # multiply-adds of the perceptron, x2
@@ -185,8 +220,20 @@ def learned_leg(args, hip, dev) -> dict:
                      "value": N * ny * nx * args.learned_steps / wall, "launch_ms": [float(v) for v in per]}
     k7_ms = res["learned"]["launch_ms"][2]
     flops = MLP_FLOPS_PER_BIN * ny * (nx // 2 + 1)
-    rows = evaluate.rmse_study(seeds=[args.seed + 9000], a_values=[2.0, 3.0, 4.0], weights=w, device=dev)
-    mean = {k: float(np.mean([r[k] for r in rows])) for k in ("forecast", "plain", "learned", "known")}
+    seeds = [args.seed + 9000 + i for i in range(args.rmse_seeds)]
+    a_values = [2.0, 2.5, 3.0, 3.5, 4.0]
+    study = {}
+    for about, what in (("centre", "truth exchangeable with the members (the paper's experiment, reading A20)"),
+                        ("truth", "members = truth + independent draws (the throughput workloads' twin, A13)")):
+        progress(f"RMSE study, {about} twins: {len(seeds) * len(a_values)} cases")
+        rows = evaluate.rmse_study(seeds=seeds, a_values=a_values, weights=w, about=about, device=dev)
+        study[about] = {
+            "twin": what,
+            "mean": {k: float(np.mean([r[k] for r in rows])) for k in ("forecast", "plain", "learned", "known")},
+            "learned_vs_plain": evaluate.paired_summary(rows, "learned", "plain"),
+            "known_vs_plain": evaluate.paired_summary(rows, "known", "plain"),
+            "cases": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()} for r in rows],
+        }
     return {
         "workload": "2048x2048 grid, N=5 members, float32, spectrum |k|^-3, R=0.05 I (R_spec array)",
         "unit": "member-gridpoints/s",
@@ -196,9 +243,10 @@ def learned_leg(args, hip, dev) -> dict:
         "perceptron": {"bound": "mfma", "dtype": "bf16", "flops": flops, "ms": k7_ms,
                        "achieved": flops / (k7_ms * 1e-3) / 1e12, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": flops / (k7_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS},
-        "rmse": {"metric": "RMSE of the analysis ensemble mean vs truth", "mean": mean, "cases": rows,
-                 "twins": "held-out seeds, 2048x2048, N=5, |k|^-a, a in {2,3,4}, R=0.05 I, truth exchangeable "
-                          "with the members"},
+        "rmse": {"metric": "RMSE of the analysis ensemble mean vs truth",
+                 "twins": f"{len(seeds)} held-out seeds x a in {a_values}, 2048x2048, N=5, |k|^-a, R=0.05 I; "
+                          "paired differences (test - plain) with their standard error over the cases",
+                 **study},
         "weights": json.loads(w["meta"]) if w["meta"] else None,
     }
 
@@ -353,6 +401,8 @@ def main() -> int:
     ap.add_argument("--batch-filters", type=int, default=256, help="filters of the batched leg (0 = skip)")
     ap.add_argument("--dst-steps", type=int, default=20, help="timed analyses of the sine-basis leg (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--rmse-seeds", type=int, default=10,
+                    help="held-out seeds of the RMSE study (times 5 spectral slopes, two twin kinds)")
     ap.add_argument("--multi-steps", type=int, default=20,
                     help="timed analyses of the multi-block leg (0 = skip)")
     ap.add_argument("--learned-steps", type=int, default=20,
@@ -445,17 +495,23 @@ def main() -> int:
         "path_hbm_frac": b["path"] / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "gpu_event_ms_per_step": gpu_span_ms / args.steps,
     }
+    progress(f"main leg: {ms_per_step:.3f} ms per step")
     if args.copy_mib > 0:
         result["copy_ceiling"] = copy_ceiling(args.copy_mib, hip)
     if args.learned_steps > 0:
+        progress("learned-covariance leg")
         result["learned_covariance"] = learned_leg(args, hip, dev)
     if args.multi_steps > 0:
+        progress("multi-block leg")
         result["multiblock"] = multiblock_leg(args, hip, dev)
     if args.batch_filters > 0:
+        progress("batch leg")
         result["batch"] = batch_leg(args, dev)
     if args.dst_steps > 0:
+        progress("sine-basis leg")
         result["sine_basis"] = dst_leg(args, dev)
     if args.cpu_members > 0:
+        progress("CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(tw, min(args.cpu_members, N))
     print(json.dumps(result), flush=True)
     return 0

@@ -54,14 +54,42 @@ def rmse_case(tw: twin.Twin, weights_dev: dict, device="cuda:0") -> dict:
 
 
 def rmse_study(seeds: Iterable[int], a_values: Iterable[float], *, size: int = 2048, members: int = 5,
-               r: float = 0.05, weights: Optional[dict] = None, device="cuda:0") -> list:
-    """rmse_case over held-out twins with spectrum |k|^-a, one per (seed, a)."""
+               r: float = 0.05, weights: Optional[dict] = None, about: str = "centre", workers: int = 8,
+               device="cuda:0") -> list:
+    """rmse_case over held-out twins with spectrum |k|^-a, one per (seed, a).
+
+    about="centre": truth and members are independent perturbations of one
+    state (the paper's experiment); about="truth": the members are the truth
+    plus independent draws (the twin of the throughput workloads).  The twins
+    are generated on the host (numpy, SeedSequence; never the perceptron's
+    training generator) by a pool of threads, a few ahead of the GPU."""
+    import concurrent.futures as cf
+
     w = weights or load_weights()
     wd = _lib.mlp_weights(w, device)
+    cases = [(seed, a) for seed in seeds for a in a_values]
+
+    def make(case):
+        seed, a = case
+        return twin.make_twin(size, size, members, seed=seed, dtype=np.float32, kind="power", kw={"a": a}, r=r,
+                              about=about)
+
     rows = []
-    for seed in seeds:
-        for a in a_values:
-            tw = twin.make_twin(size, size, members, seed=seed, dtype=np.float32, kind="power", kw={"a": a}, r=r,
-                                about="centre")
-            rows.append(dict(seed=seed, a=a, **rmse_case(tw, wd, device)))
+    with cf.ThreadPoolExecutor(max(1, workers)) as ex:
+        for k0 in range(0, len(cases), workers):
+            chunk = cases[k0:k0 + workers]
+            for (seed, a), tw in zip(chunk, ex.map(make, chunk)):
+                rows.append(dict(seed=seed, a=a, **rmse_case(tw, wd, device)))
     return rows
+
+
+def paired_summary(rows: list, test: str = "learned", ref: str = "plain") -> dict:
+    """The paired comparison of two filters over the cases: wins of `test`,
+    and the mean and standard error of the difference test - ref (absolute,
+    and relative to ref)."""
+    d = np.array([r[test] - r[ref] for r in rows], dtype=np.float64)
+    rel = np.array([(r[test] - r[ref]) / r[ref] for r in rows], dtype=np.float64)
+    n = len(d)
+    se = (lambda x: float(x.std(ddof=1) / np.sqrt(n)) if n > 1 else float("nan"))
+    return {"cases": n, "wins": int((d < 0).sum()), "mean_diff": float(d.mean()), "se_diff": se(d),
+            "mean_rel_diff": float(rel.mean()), "se_rel_diff": se(rel)}

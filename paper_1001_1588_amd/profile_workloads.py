@@ -44,9 +44,9 @@ def write(s: dict, bj: dict, outdir: str) -> None:
     cmds = f'''## Commands (run from /tmp with TMPDIR=/tmp; R = repository root, O = output folder)
 
 ```
-rocprofv3 --kernel-trace --stats -d O/trace -o run --output-format csv -- python3 R/bench.py --steps 20 --warmup 3 --cpu-members 0 --learned-steps 10 --multi-steps 10 --batch-steps 5 --dst-steps 10
-rocprofv3 --pmc FETCH_SIZE -d O/fetch -o run --output-format csv -- python3 R/bench.py --steps 2 --warmup 1 --cpu-members 0 --learned-steps 2 --multi-steps 2 --batch-steps 2 --dst-steps 2
-rocprofv3 --pmc WRITE_SIZE -d O/write -o run --output-format csv -- python3 R/bench.py --steps 2 --warmup 1 --cpu-members 0 --learned-steps 2 --multi-steps 2 --batch-steps 2 --dst-steps 2
+rocprofv3 --kernel-trace --stats -d O/trace -o run --output-format csv -- python3 R/bench.py --steps 20 --warmup 3 --cpu-members 0 --learned-steps 10 --rmse-seeds 1 --multi-steps 10 --batch-steps 5 --dst-steps 10
+rocprofv3 --pmc FETCH_SIZE -d O/fetch -o run --output-format csv -- python3 R/bench.py --steps 2 --warmup 1 --cpu-members 0 --learned-steps 2 --rmse-seeds 1 --multi-steps 2 --batch-steps 2 --dst-steps 2
+rocprofv3 --pmc WRITE_SIZE -d O/write -o run --output-format csv -- python3 R/bench.py --steps 2 --warmup 1 --cpu-members 0 --learned-steps 2 --rmse-seeds 1 --multi-steps 2 --batch-steps 2 --dst-steps 2
 python -m paper_1001_1588_amd.profile_summary O --copy-mib 1024 --json R/profiles/kernels_traffic.json
 python3 R/bench.py > O/bench.json
 python -m paper_1001_1588_amd.profile_workloads R/profiles/kernels_traffic.json O/bench.json R/profiles
@@ -55,7 +55,7 @@ python -m paper_1001_1588_amd.profile_workloads R/profiles/kernels_traffic.json 
 Counters are KiB per dispatch.  On bench.py's plain 1 GiB device copy (the largest `__amd_rocclr_copyBuffer` dispatch) FETCH_SIZE and WRITE_SIZE read {(1<<30)/s['copy_scale']['fetch']:.0f} and {(1<<30)/s['copy_scale']['write']:.0f} for 1 GiB read and 1 GiB written, so fetches are scaled by {s['copy_scale']['fetch']:.1f} bytes per counter unit and writes by {s['copy_scale']['write']:.0f}.  Algorithmic bytes are each launch's inputs read once plus its outputs written once.  Rows are keyed by kernel and total threads (one kernel serves several workloads).
 '''
     n = 2048*2048; h = 2048*1025*8; r4 = 2048*1025*4
-    K1, K2, K3 = ('fftenkf::k1_forward<float, 2048, 16, 4, false>', 688128), ('fftenkf::k2_spectral<float, 128, 20, false>', 524800), ('fftenkf::k3_inverse<float, 2048, 16, 4, false>', 655360)
+    K1, K2, K3 = ('fftenkf::k1_forward<float, 2048, 16, 4, false>', 688128), ('fftenkf::k2_spectral<float, 128, 20, 0>', 524288), ('fftenkf::k3_inverse<float, 2048, 16, 4, false>', 655360)
     tr = [get(*k) for k in (K1, K2, K3)]
     tb = sum(k['fetch_bytes'] + k['write_bytes'] for k in tr); tt = sum(k['avg_ns'] for k in tr)
     out = {}
@@ -84,12 +84,12 @@ Workload: periodic 2048x2048 grid, N = 5, float32, spectrum |k|^-3, R = 0.05 I (
 
 {hdr}
 {row('fftenkf::k1_forward<float, 2048, 16, 4, false>', 196608, 6*n*4 + 6*h5)}
-{row('fftenkf::k2_spectral<float, 128, 8, true>', 524800, 6*h5 + r4)}
+{row('fftenkf::k2_spectral<float, 128, 8, 2>', 524288, 6*h5 + r4)}
 {row('fftenkf::k7_spectral_mlp', 131072, 2048*1025*4*2)}
-{row('fftenkf::k2_spectral<float, 128, 8, false>', 524800, 6*h5 + r4 + 5*h5)}
+{row('fftenkf::k2_spectral<float, 128, 8, 1>', 524288, 6*h5 + r4 + 5*h5)}
 {row('fftenkf::k3_inverse<float, 2048, 16, 4, false>', 163840, 5*h5 + 5*n*4)}
 
-`k2_spectral<float, 128, 8, true>` is the statistics-only pass (reads 6 spectra, writes c_hat).  `k2_spectral<float, 128, 8, false>` is the update pass with the perceptron's spectrum and also the single-pass analyses of the RMSE study.  The perceptron is bound by its arithmetic, not by HBM: 41.6 GFLOP per launch, {mlp['avg_ns']/1e3:.1f} us average here, {41.648e9/(mlp['avg_ns']*1e-9)/1e12:.0f} TFLOP/s of bf16 matrix work ({41.648e9/(mlp['avg_ns']*1e-9)/1e12/2500*100:.0f}% of 2.5 PFLOP/s).
+`k2_spectral<float, 128, 8, 2>` is the statistics-only pass (reads 6 spectra, writes c_hat).  `k2_spectral<float, 128, 8, 1>` is the update pass with the perceptron's spectrum (the variant with a given spectrum; the RMSE study's exact-covariance analyses run it too, and its plain analyses `k2_spectral<float, 128, 8, 0>`).  The perceptron is bound by its arithmetic, not by HBM: 41.6 GFLOP per launch, {mlp['avg_ns']/1e3:.1f} us average here, {41.648e9/(mlp['avg_ns']*1e-9)/1e12:.0f} TFLOP/s of bf16 matrix work ({41.648e9/(mlp['avg_ns']*1e-9)/1e12/2500*100:.0f}% of 2.5 PFLOP/s).
 '''
     n1 = 1024*1024; h1 = 1024*513*8
     out['multiblock4x1024_n10_sweeps.md'] = f'''# rocprofv3 summary: the multi-block analysis on 4 fields of 1024x1024, N=10, float32
@@ -101,7 +101,7 @@ Workload: 4 blocks of 1024x1024, N = 10, float32, spectra (1+|k|^2/L_b^2)^-2 wit
 
 {hdr}
 {row(*first(('fftenkf::k1_forward<float, 1024, 8, 4, false>', 671744), ('fftenkf::k1_forward<float, 1024, 16, 8, false>', 335872)), 41*n1*4 + 41*h1)}
-{row(*first(('fftenkf::k10_observed<float, 128, 10, 1>', 131328), ('fftenkf::k10_observed<float, 64, 10, 1>', 131328)), 41*h1 + 1024*513*4 + 40*h1)}
+{row(*first(('fftenkf::k10_observed<float, 128, 10, 1>', 131072), ('fftenkf::k10_observed<float, 64, 10, 1>', 131072)), 41*h1 + 1024*513*4 + 40*h1)}
 {row(*first(('fftenkf::k3_inverse<float, 1024, 8, 4, false>', 655360), ('fftenkf::k3_inverse<float, 1024, 16, 8, false>', 327680)), 40*h1 + 40*n1*4)}
 '''
     out['sine2048_n20_sweeps.md'] = f'''# rocprofv3 summary: the analysis in the real sine basis on 2048x2048, N=20, float32
@@ -113,11 +113,11 @@ Workload: the main leg's ensemble (2048x2048, N = 20, float32, |k|^-3), R = 0.05
 
 {hdr}
 {row('fftenkf::k1_forward<float, 2048, 16, 4, true>', 688128, 21*n*4 + 21*h)}
-{row('fftenkf::k2_spectral<float, 128, 20, true>', 524800, 21*h + 21*h + r4)}
+{row('fftenkf::k2_spectral<float, 128, 20, 2>', 524288, 21*h + 21*h + r4)}
 {row('fftenkf::dst_quad<float, 20>', 1050880, 21*h + 20*h)}
 {row('fftenkf::k3_inverse<float, 2048, 16, 4, true>', 655360, 20*h + 20*n*4)}
 
-Sweeps 1 and 3 read and write the fields through the sine reordering (`true` in their names).  `k2_spectral<float, 128, 20, true>` averages the statistics launch (21 spectra in and out, the algorithmic bytes in the table) and the inverse-only launch (20 in and out).
+Sweeps 1 and 3 read and write the fields through the sine reordering (`true` in their names).  `k2_spectral<float, 128, 20, 2>` (the variant of the statistics and inverse-only modes) averages the statistics launch (21 spectra in and out, the algorithmic bytes in the table) and the inverse-only launch (20 in and out).
 '''
     for name, text in out.items():
         open(os.path.join(outdir, name), 'w').write(text)
