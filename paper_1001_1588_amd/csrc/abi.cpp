@@ -671,14 +671,14 @@ int run_batch(int N, int dtype, const fftenkf_filter* fs, int n, const std::vect
   return FFTENKF_OK;
 }
 
-// Workspace of the sine-basis analysis: the spectral workspace, then the
-// reordered fields v of Makhoul's form ((N+1) planes of ny * nx reals).
 // The sine-basis analysis uses the periodic analysis' workspace.
 size_t dst_ws_bytes(const Plan& plan, int, int, int, int) { return plan.ws_bytes; }
 
-// Sweep 1 through the sine reordering, the statistics mode of sweep 2, the
-// per-bin sine-basis kernel, then (for an analysis) the inverse-only mode of
-// sweep 2 and sweep 3 back through the reordering.
+// Sweep 1 through the sine reordering; then, on the shapes it takes, the fused
+// sine-basis sweep (k11_dst_fused.hpp) and sweep 3 back through the
+// reordering.  Otherwise (and for the coefficient export) the statistics mode of
+// sweep 2, the per-bin sine-basis kernel, then (for an analysis) the
+// inverse-only mode of sweep 2 and sweep 3.
 int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void* R_dst, uint64_t seed, void* out,
             void* dbg_coeffs) {
   if (t_fail_next != 0) {
@@ -695,6 +695,19 @@ int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void
   const int N = e->n_members, ny = e->ny, nx = e->nx;
   K1Args a1{e->members, data, N, ny, nx, plan.R, plan.L, ws_main, tab, 1};
   err = e->dtype == FFTENKF_F32 ? launch_k1_f32(a1, stream) : launch_k1_f64(a1, stream);
+  K9Args a9{ws_main, R_dst, e->r_scalar, N, ny, nx, plan.R, plan.L,
+            (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), dbg_coeffs};
+  a9.tab = tab;
+  a9.main_bytes = (uint32_t)(plan.main_elems * 2 * dsize(e->dtype));
+  if (dbg_coeffs == nullptr && k11_supports(plan.L, nx)) {
+    // the spectral part as one sweep: transforms, eq. (2)-(3) on the sine
+    // coefficients, inverse transforms
+    if (err == hipSuccess) err = launch_k11(a9, e->dtype, stream);
+    K3Args a3{ws_main, N, ny, nx, plan.R, plan.L, out, tab, 1};
+    if (err == hipSuccess) err = e->dtype == FFTENKF_F32 ? launch_k3_f32(a3, stream) : launch_k3_f64(a3, stream);
+    if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "sine-basis analysis launch: %s", hipGetErrorString(err));
+    return FFTENKF_OK;
+  }
   K2Args a2{};
   a2.ws_main = ws_main;
   a2.r_scalar = 1.0;
@@ -705,8 +718,6 @@ int run_dst(const fftenkf_ens* e, const Plan& plan, const void* data, const void
   a2.mode = K2_STATS;
   auto k2 = [&]() { return e->dtype == FFTENKF_F32 ? launch_k2_f32(a2, stream) : launch_k2_f64(a2, stream); };
   if (err == hipSuccess) err = k2();
-  K9Args a9{ws_main, R_dst, e->r_scalar, N, ny, nx, plan.R, plan.L,
-            (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), dbg_coeffs};
   if (err == hipSuccess) err = launch_dst_quad(a9, e->dtype, stream);
   if (err == hipSuccess && dbg_coeffs == nullptr) {
     a2.mode = K2_INVERSE;

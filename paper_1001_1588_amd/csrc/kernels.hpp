@@ -183,8 +183,16 @@ struct K9Args {
   int N, ny, nx, R, L;
   uint32_t key0, key1;
   void* dbg_coeffs;  // test export: [N+1][ny][nx] orthonormal sine coefficients, or nullptr
+  const void* tab = nullptr;  // W_4096^k (the fused sweep)
+  uint32_t main_bytes = 0;    // size of the spectral region (the fused sweep)
+  int group_xcd = 1;          // the fused sweep's XCD grouping of blocks sharing 128-byte lines
 };
 hipError_t launch_dst_quad(const K9Args& a, int dtype, hipStream_t s);
+// The sine-basis analysis as one spectral sweep (k11_dst_fused.hpp) for the
+// shapes it takes (L >= 16, nx/2 a multiple of 512 / L); hipErrorNotSupported
+// otherwise.
+hipError_t launch_k11(const K9Args& a, int dtype, hipStream_t s);
+bool k11_supports(int L, int nx);
 
 // Device address of the W_4096^k table (float2 for dtype 0, double2 for 1) on
 // the current device, filled from float64 host values on first use.
