@@ -36,6 +36,8 @@ SOURCES = {
                               CSRC + "k10_observed.hpp"],
     "k7_spectral_mlp": [CSRC + "kernels.hpp", CSRC + "k7_spectral_mlp.hip"],
     "dst_": [CSRC + "fft_core.hpp", CSRC + "kernels.hpp", CSRC + "philox.hpp", CSRC + "k9_dst.hip"],
+    "k11_dst_fused": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "k2_spectral.hpp",
+                               CSRC + "k11_dst_fused.hpp"],
 }
 COPY = "__amd_rocclr_copyBuffer"
 

@@ -113,11 +113,10 @@ Workload: the main leg's ensemble (2048x2048, N = 20, float32, |k|^-3), R = 0.05
 
 {hdr}
 {row('fftenkf::k1_forward<float, 2048, 16, 4, true>', 688128, 21*n*4 + 21*h)}
-{row('fftenkf::k2_spectral<float, 128, 20, 2>', 524288, 21*h + 21*h + r4)}
-{row('fftenkf::dst_quad<float, 20>', 1050880, 21*h + 20*h)}
+{row('fftenkf::k11_dst_fused<float, 128, 20>', 589824, 21*h + 20*h)}
 {row('fftenkf::k3_inverse<float, 2048, 16, 4, true>', 655360, 20*h + 20*n*4)}
 
-Sweeps 1 and 3 read and write the fields through the sine reordering (`true` in their names).  `k2_spectral<float, 128, 20, 2>` (the variant of the statistics and inverse-only modes) averages the statistics launch (21 spectra in and out, the algorithmic bytes in the table) and the inverse-only launch (20 in and out).
+Sweeps 1 and 3 read and write the fields through the sine reordering (`true` in their names).  `k11_dst_fused` is the whole spectral part of the sine-basis analysis (length-L transforms, eq. (2)-(3) on the sine coefficients, inverse transforms): 21 spectra in, 20 out.  Its grid is (R/2 + 1) row pairs x (nx/2)/4 column chunks of 256 threads, 12.5% more blocks than a single-block sweep because rows 0 and R/2 pair with themselves.
 '''
     for name, text in out.items():
         open(os.path.join(outdir, name), 'w').write(text)
