@@ -120,20 +120,22 @@ size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 // Default rows per sweep-1/3 tile (the tile schedule ny = R * L).  Timed with
 // the autotuner at N = 5 to 20: R = 8 is faster for every float32 grid up to
 // 1024 wide, and R = 16 for 2048-wide grids from N = 16 up (at N = 5 there R = 8
-// is faster; fftenkf_set_tile_rows overrides per grid).
+// is faster; fftenkf_set_tile_rows overrides per grid, among the compiled
+// choices of tile_rows_options).
 int rows_per_tile(int dtype, int nx) {
   if (dtype == FFTENKF_F32) return nx == 2048 ? 16 : 8;
   return nx <= 2048 ? 8 : 4;
 }
 
 // Row counts R of the sweep-1/3 tiles compiled for a dtype and nx (each also
-// needs R <= ny).
+// needs R <= ny and ny / R <= 512, the longest transform of the spectral sweeps).
 int tile_rows_options(int dtype, int nx, int* out) {
   if (dtype == FFTENKF_F32) {
     if (nx <= 2048) {
-      out[0] = 8;
-      out[1] = 16;
-      return 2;
+      out[0] = 4;
+      out[1] = 8;
+      out[2] = 16;
+      return 3;
     }
     out[0] = 8;
     return 1;
@@ -141,6 +143,8 @@ int tile_rows_options(int dtype, int nx, int* out) {
   out[0] = nx <= 2048 ? 8 : 4;
   return 1;
 }
+
+bool tile_rows_fit(int rows, int ny) { return rows <= ny && ny / rows <= 512; }
 
 // Tile rows chosen by a tuner for a grid, process-wide; the default otherwise.
 std::mutex g_tune_mu;
@@ -1088,7 +1092,7 @@ int fftenkf_tile_rows_options(int ny, int nx, int dtype, int* rows, int capacity
   const int n = tile_rows_options(dtype, nx, all);
   int k = 0;
   for (int i = 0; i < n; ++i)
-    if (all[i] <= ny) {
+    if (tile_rows_fit(all[i], ny)) {
       if (rows != nullptr && k < capacity) rows[k] = all[i];
       ++k;
     }
@@ -1112,7 +1116,7 @@ int fftenkf_set_tile_rows(int ny, int nx, int dtype, int rows) {
   int all[4];
   const int n = tile_rows_options(dtype, nx, all);
   for (int i = 0; i < n; ++i)
-    if (all[i] == rows && rows <= ny) {
+    if (all[i] == rows && tile_rows_fit(rows, ny)) {
       g_tune[key] = rows;
       return FFTENKF_OK;
     }

@@ -4,6 +4,7 @@ template <int NX>
 static hipError_t k3_f32_R(const K3Args& a, int R, hipStream_t s) {
   if constexpr (NX <= 2048) {
     if (R == 16) return launch_k3_shape<float, NX, 16>(a, s);
+    if (R == 4) return launch_k3_shape<float, NX, 4>(a, s);
   }
   if (R == 8) return launch_k3_shape<float, NX, 8>(a, s);
   return hipErrorInvalidValue;
@@ -28,6 +29,7 @@ template <int NX>
 static hipError_t k3_f32_R_batch(const BatchArgs& a, int R, hipStream_t s) {
   if constexpr (NX <= 2048) {
     if (R == 16) return launch_k3_batch_shape<float, NX, 16>(a, s);
+    if (R == 4) return launch_k3_batch_shape<float, NX, 4>(a, s);
   }
   if (R == 8) return launch_k3_batch_shape<float, NX, 8>(a, s);
   return hipErrorInvalidValue;

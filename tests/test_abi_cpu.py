@@ -198,13 +198,17 @@ def test_batch_validation_and_tuning(built_lib):
     assert lib.fftenkf_analyze_batch(4, 0, (_lib.Filter * 1)(bad), 1, None) == _lib.EUNSUPPORTED
     assert lib.fftenkf_analyze_batch(4, 0, arr, 0, None) == _lib.OK             # nothing to do
     buf = (ctypes.c_int * 4)()
-    assert lib.fftenkf_tile_rows_options(256, 256, 0, buf, 4) == 2 and list(buf[:2]) == [8, 16]
-    assert lib.fftenkf_tile_rows_options(8, 64, 0, buf, 4) == 1 and buf[0] == 8       # R <= ny
+    assert lib.fftenkf_tile_rows_options(256, 256, 0, buf, 4) == 3 and list(buf[:3]) == [4, 8, 16]
+    assert lib.fftenkf_tile_rows_options(8, 64, 0, buf, 4) == 2 and list(buf[:2]) == [4, 8]  # R <= ny
+    assert lib.fftenkf_tile_rows_options(4096, 1024, 0, buf, 4) == 2 and list(buf[:2]) == [8, 16]  # ny / R <= 512
     assert lib.fftenkf_tile_rows_options(64, 4096, 0, buf, 4) == 1 and buf[0] == 8
     assert lib.fftenkf_tile_rows(256, 256, 0) == 8 and lib.fftenkf_tile_rows(2048, 2048, 0) == 16
     assert lib.fftenkf_set_tile_rows(256, 256, 0, 16) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 16
     assert lib.fftenkf_set_tile_rows(256, 256, 0, 0) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 8
-    assert lib.fftenkf_set_tile_rows(256, 256, 0, 4) == _lib.EUNSUPPORTED
+    assert lib.fftenkf_set_tile_rows(256, 256, 0, 32) == _lib.EUNSUPPORTED
+    assert lib.fftenkf_set_tile_rows(4096, 1024, 0, 4) == _lib.EUNSUPPORTED      # a 1024-point transform
+    assert lib.fftenkf_set_tile_rows(256, 256, 0, 4) == _lib.OK and lib.fftenkf_tile_rows(256, 256, 0) == 4
+    assert lib.fftenkf_set_tile_rows(256, 256, 0, 0) == _lib.OK
 
 
 def test_dst_validation(built_lib):

@@ -99,7 +99,7 @@ def test_tile_rows_change_rounding_only():
     tw = twin.random_ensemble(256, 256, 8, seed=11, dtype=np.float32)
     e, d = dev(tw.ens), dev(tw.data)
     opts = _lib.tile_rows_options(256, 256, torch.float32)
-    assert opts == [8, 16]
+    assert opts == [4, 8, 16]
     outs = []
     try:
         for r in opts:
