@@ -257,7 +257,16 @@ typedef struct fftenkf_filter {
 /* Enqueues every filter's analysis on `stream` (hipStream_t, NULL = default).
  * Arguments are validated first (as for fftenkf_analyze, per filter; what a
  * filter writes may overlap no other buffer of the batch); on error nothing is
- * enqueued. */
+ * enqueued.  When the batch has more than one launch chain (more than one grid
+ * size, or more than 40 filters of one), the chains run on up to three
+ * library-owned streams of the device, forked from `stream` by an event and
+ * joined back into it: work queued on `stream` before the call happens before
+ * the batch and work queued after it sees the finished outputs, as with a
+ * single stream, and under stream capture the fork and join become graph
+ * dependencies.  The streams are made on the first such call outside a
+ * capture (until then, and if they cannot be made, the chains run one after
+ * another on `stream`) and kept until the process ends; batches issued on
+ * different streams share them and so run one after the other. */
 int fftenkf_analyze_batch(int n_members, int dtype, const fftenkf_filter* filters, int n_filters, void* stream);
 
 /*

@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -623,8 +624,46 @@ void filter_regions(const fftenkf_filter& f, int N, int dtype, const Plan& plan,
   r[4] = {f.workspace, plan.ws_bytes, "workspace"};
 }
 
+// Streams beside the caller's for the launch chains of a batch, per device,
+// made on the first batch that is not being captured (stream and event
+// creation stay out of a capture).  Default priority, non-blocking.
+constexpr int kSideStreams = 3;
+struct SidePool {
+  hipStream_t s[kSideStreams];
+  hipEvent_t fork, join[kSideStreams];
+};
+std::mutex g_side_mu;
+std::map<int, SidePool> g_side;
+
+// The pool of the current device, or nullptr if there is none and one cannot
+// be made now (under capture, or on a creation failure).  g_side_mu held.
+const SidePool* side_pool(hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  auto it = g_side.find(dev);
+  if (it != g_side.end()) return &it->second;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  SidePool p{};
+  bool ok = hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; k < kSideStreams && ok; ++k)
+    ok = hipStreamCreateWithFlags(&p.s[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&p.join[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    return nullptr;  // what was made is kept until the process ends
+  }
+  return &g_side.emplace(dev, p).first->second;
+}
+
 // The three sweeps of every filter: filters on the same grid share launches,
-// kMaxBatch at a time, blockIdx.y selecting the filter.
+// kMaxBatch at a time, blockIdx.y selecting the filter.  Each such chain of
+// three launches is independent of the others; with more than one chain they
+// run on side streams forked from `stream` and joined back into it (largest
+// chains first, each to the least loaded side stream), so a small grid's
+// launches run beside a large grid's rather than after them and the end of one
+// launch overlaps the others.  Under stream capture this records the same fork
+// and join as graph dependencies.
 int run_batch(int N, int dtype, const fftenkf_filter* fs, int n, const std::vector<Plan>& plans, hipStream_t stream) {
   if (t_fail_next != 0) {
     const int st = t_fail_next;
@@ -636,43 +675,85 @@ int run_batch(int N, int dtype, const fftenkf_filter* fs, int n, const std::vect
   if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "twiddle table: %s", hipGetErrorString(err));
   std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int i = 0; i < n; ++i) groups[std::make_pair(fs[i].ny, fs[i].nx)].push_back(i);
-  for (const auto& g : groups) {
-    const std::vector<int>& idx = g.second;
-    const Plan& plan = plans[idx[0]];
-    for (size_t c0 = 0; c0 < idx.size(); c0 += kMaxBatch) {
-      BatchArgs b{};
-      b.count = (int)std::min<size_t>(kMaxBatch, idx.size() - c0);
-      b.N = N;
-      b.ny = g.first.first;
-      b.nx = g.first.second;
-      b.L = plan.L;
-      b.tab = tab;
-      K2Args& a2 = b.k2;
-      set_k2_geometry(a2, plan, N, b.ny, b.nx, dtype);
-      a2.mode = K2_ANALYZE;
-      a2.tab = tab;
-      for (int k = 0; k < b.count; ++k) {
-        const fftenkf_filter& f = fs[idx[c0 + k]];
-        char* ws = static_cast<char*>(f.workspace);
-        BatchFilter& bf = b.f[k];
-        bf.members = f.members;
-        bf.data = f.data;
-        bf.R_spec = f.R_spec;
-        bf.out = f.out;
-        bf.ws_main = ws;
-        bf.r_scalar = f.r_scalar;
-        bf.key0 = (uint32_t)(f.seed & 0xFFFFFFFFu);
-        bf.key1 = (uint32_t)(f.seed >> 32);
-      }
-      err = dtype == FFTENKF_F32 ? launch_k1_batch_f32(b, plan.R, stream) : launch_k1_batch_f64(b, plan.R, stream);
-      if (err == hipSuccess) err = launch_k2_batch(b, dtype, stream);
-      if (err == hipSuccess)
-        err = dtype == FFTENKF_F32 ? launch_k3_batch_f32(b, plan.R, stream) : launch_k3_batch_f64(b, plan.R, stream);
-      if (err != hipSuccess)
-        return fail(FFTENKF_EDEVICE, "batch launch (%d x %d): %s", b.ny, b.nx, hipGetErrorString(err));
+  struct Chain {
+    int plan;
+    std::vector<int> idx;
+    double cost;
+  };
+  std::vector<Chain> chains;
+  for (const auto& g : groups)
+    for (size_t c0 = 0; c0 < g.second.size(); c0 += kMaxBatch) {
+      Chain c;
+      c.plan = g.second[0];
+      c.idx.assign(g.second.begin() + c0, g.second.begin() + std::min(g.second.size(), c0 + kMaxBatch));
+      c.cost = (double)c.idx.size() * g.first.first * g.first.second;
+      chains.push_back(std::move(c));
+    }
+  std::stable_sort(chains.begin(), chains.end(), [](const Chain& a, const Chain& b) { return a.cost > b.cost; });
+
+  auto launch_chain = [&](const Chain& c, hipStream_t st) -> hipError_t {
+    const Plan& plan = plans[c.plan];
+    BatchArgs b{};
+    b.count = (int)c.idx.size();
+    b.N = N;
+    b.ny = fs[c.idx[0]].ny;
+    b.nx = fs[c.idx[0]].nx;
+    b.L = plan.L;
+    b.tab = tab;
+    K2Args& a2 = b.k2;
+    set_k2_geometry(a2, plan, N, b.ny, b.nx, dtype);
+    a2.mode = K2_ANALYZE;
+    a2.tab = tab;
+    for (int k = 0; k < b.count; ++k) {
+      const fftenkf_filter& f = fs[c.idx[k]];
+      BatchFilter& bf = b.f[k];
+      bf.members = f.members;
+      bf.data = f.data;
+      bf.R_spec = f.R_spec;
+      bf.out = f.out;
+      bf.ws_main = f.workspace;
+      bf.r_scalar = f.r_scalar;
+      bf.key0 = (uint32_t)(f.seed & 0xFFFFFFFFu);
+      bf.key1 = (uint32_t)(f.seed >> 32);
+    }
+    hipError_t e = dtype == FFTENKF_F32 ? launch_k1_batch_f32(b, plan.R, st) : launch_k1_batch_f64(b, plan.R, st);
+    if (e == hipSuccess) e = launch_k2_batch(b, dtype, st);
+    if (e == hipSuccess)
+      e = dtype == FFTENKF_F32 ? launch_k3_batch_f32(b, plan.R, st) : launch_k3_batch_f64(b, plan.R, st);
+    if (e != hipSuccess) fail(FFTENKF_EDEVICE, "batch launch (%d x %d): %s", b.ny, b.nx, hipGetErrorString(e));
+    return e;
+  };
+
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  const SidePool* pool = chains.size() > 1 ? side_pool(stream) : nullptr;
+  if (pool == nullptr) {
+    for (const Chain& c : chains)
+      if (launch_chain(c, stream) != hipSuccess) return FFTENKF_EDEVICE;
+    return FFTENKF_OK;
+  }
+  const int K = (int)std::min<size_t>(kSideStreams, chains.size());
+  err = hipEventRecord(pool->fork, stream);
+  for (int k = 0; k < K && err == hipSuccess; ++k) err = hipStreamWaitEvent(pool->s[k], pool->fork, 0);
+  if (err != hipSuccess) return fail(FFTENKF_EDEVICE, "batch fork: %s", hipGetErrorString(err));
+  double load[kSideStreams] = {};
+  int st = FFTENKF_OK;
+  for (const Chain& c : chains) {
+    int k = 0;
+    for (int j = 1; j < K; ++j)
+      if (load[j] < load[k]) k = j;
+    load[k] += c.cost;
+    if (launch_chain(c, pool->s[k]) != hipSuccess) {
+      st = FFTENKF_EDEVICE;
+      break;
     }
   }
-  return FFTENKF_OK;
+  // always join every side stream that was forked, so a capture can end
+  for (int k = 0; k < K; ++k) {
+    hipError_t e = hipEventRecord(pool->join[k], pool->s[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(stream, pool->join[k], 0);
+    if (e != hipSuccess && st == FFTENKF_OK) st = fail(FFTENKF_EDEVICE, "batch join: %s", hipGetErrorString(e));
+  }
+  return st;
 }
 
 // The sine-basis analysis uses the periodic analysis' workspace.

@@ -5,7 +5,9 @@ arguments (the same kernels run, with the filter chosen by the launch's second
 grid dimension), and within the single-filter bar (1e-5 relative L2 in float32,
 1e-10 in float64) of the float64 oracle.  A captured graph replayed several
 times, with eager work between the replays, reproduces the eager result every
-time.  The tile schedule chosen by the tuner changes the rounding only."""
+time.  Launch chains of different grids run on side streams forked from and
+joined into the caller's, which orders the batch with the caller's own work.
+The tile schedule chosen by the tuner changes the rounding only."""
 
 import numpy as np
 import pytest
@@ -82,6 +84,32 @@ def test_graph_replays_match_eager():
         for i in range(len(shapes)):
             assert torch.equal(outs[i], eager[i]), f"replay {rep}, filter {i}"
         del junk
+
+
+def test_batch_orders_with_the_callers_stream():
+    """Filters of several grid sizes run on streams forked from the caller's
+    and joined back into it: inputs written on the caller's stream just before
+    the batch are the ones analysed, and work queued on that stream right after
+    it reads the finished outputs (no device synchronisation in between)."""
+    shapes = [(1024, 1024), (64, 64), (256, 256), (128, 128), (512, 512)]
+    tws, ens, data, R = make_batch(shapes, 8, np.float32, seed=650)
+    refs = [_lib.analyze(ens[i], data[i], R[i], tws[i].seed).clone() for i in range(len(shapes))]
+    torch.cuda.synchronize()
+    src = [e.clone() for e in ens]
+    b = _lib.Batch(ens, data, R, [t.seed for t in tws])
+    for rep in range(3):
+        for e in ens:
+            e.fill_(7.0)                     # overwritten below on the same stream
+        torch.cuda.synchronize()
+        for e, s in zip(ens, src):
+            e.copy_(s)                       # queued, not waited for
+        outs = b.run()
+        after = [o.clone() for o in outs]    # queued behind the batch's join
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        for i in range(len(shapes)):
+            assert torch.equal(after[i], refs[i]), f"rep {rep}, filter {i} ({shapes[i]})"
 
 
 def test_in_place_batch():
