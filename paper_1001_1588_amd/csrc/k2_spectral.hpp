@@ -25,6 +25,7 @@
 #include "kernels.hpp"
 #include "philox.hpp"
 #include "spectral_unit.hpp"
+#include "wave_fft.hpp"
 
 namespace fftenkf {
 
@@ -128,9 +129,14 @@ enum { K2V_PLAIN = 0, K2V_LAM = 1, K2V_SPLIT = 2 };
 // The work of one block; `unit` is its index within one analysis.  FOLD:
 // carry the split and join of packed rows and the pair slots (needed only by
 // the units with g.fold); the analysis kernels run the body without them in
-// every other unit, which keeps its registers to the common case.
-template <typename T, int L, int NMAX, int VAR, bool FOLD = true>
+// every other unit, which keeps its registers to the common case.  WF: the
+// length-128 transforms of wave_fft.hpp (float32 units of eight columns
+// without a packed column), whose bins sit at wave_fft128_bin rather than in
+// natural order; loads and stores are the same.
+template <typename T, int L, int NMAX, int VAR, bool FOLD = true, bool WF = false>
 __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
+  static_assert(!WF || (L == 128 && !FOLD && VAR != K2V_SPLIT && std::is_same<T, float>::value),
+                "the wave-level transform serves float32 analysis units of length 128");
   constexpr bool SPLIT = VAR == K2V_SPLIT;
   const void* const lam_map = VAR == K2V_PLAIN ? nullptr : a.lam_map;
   constexpr int P = k2_points(L);
@@ -167,6 +173,30 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   const V2<T>* const tw = copy_twiddles<T, L>(lds0 + 2 * FB * SEQP, tab);
   V2<T>* const xch = lds0 + 2 * FB * SEQP + L;  // two buffers of FB x L, used in turn
   int xpar = 0;
+  WaveFft128 wf;
+  if constexpr (WF) {
+    lds_barrier();  // the twiddle copy, read by every thread before any exchange
+    wf.init(reinterpret_cast<const V2<float>*>(tw), t2);
+  }
+  // the length-L transforms of FB2 fields through the current exchange buffer
+  auto fwd = [&](auto& blk) __attribute__((always_inline)) {
+    constexpr int FB2 = sizeof(blk) / sizeof(blk[0]);
+    if constexpr (WF) {
+      wave_fft128_forward<FB2>(blk, wf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
+      lp.parity ^= 1;
+    } else {
+      fft_forward<T, L, P, FB2, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+    }
+  };
+  auto inv = [&](auto& blk) __attribute__((always_inline)) {
+    constexpr int FB2 = sizeof(blk) / sizeof(blk[0]);
+    if constexpr (WF) {
+      wave_fft128_inverse<FB2>(blk, wf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
+      lp.parity ^= 1;
+    } else {
+      fft_inverse<T, L, P, FB2, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+    }
+  };
 
   // load: members into u, data into dv (first-pass layout)
   cx<T> u[NMAX][P];
@@ -194,7 +224,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
         for (int b = 0; b < FB; ++b)
 #pragma unroll
           for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
-        fft_forward<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+        fwd(blk);
         if (FOLD && g.fold) fold_exchange<T, FB, FB, P, TF2, L>(blk, xch, xpar, t2, xlane, k2, true);
 #pragma unroll
         for (int b = 0; b < FB; ++b)
@@ -202,7 +232,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
           for (int i = 0; i < P; ++i) u[f0 + b][i] = blk[b][i];
       }
     }
-    fft_forward<T, L, P, 1, SEQP, false, Lay, L>(dv, t2, lp, C, tw);
+    fwd(dv);
     if (FOLD && g.fold) fold_exchange<T, 1, FB, P, TF2, L>(dv, xch, xpar, t2, xlane, k2, true);
   }
 
@@ -227,7 +257,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   T csum = T(0);
 #pragma unroll
   for (int i = 0; i < P; ++i) {
-    const int r = t2 + TF2 * i;
+    const int r = WF ? wave_fft128_bin(t2, i) : t2 + TF2 * i;
     const int ky = cb.kyb + R * r, kxb = FOLD ? (r > cb.thr ? nxh : kx) : kxt;
     const bool pr = FOLD && (i == 0 ? cb.pair0 : (i == P / 2 ? cb.pairh : false));
     const size_t bin = (size_t)ky * nh + kxb, bin_n = (size_t)ky * nh + nxh;
@@ -385,7 +415,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
 #pragma unroll
         for (int i = 0; i < P; ++i) blk[b][i] = u[f0 + b][i];
       if (FOLD && g.fold) fold_exchange<T, FB, FB, P, TF2, L>(blk, xch, xpar, t2, xlane, k2, false);
-      fft_inverse<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+      inv(blk);
       // kx < nx/2 always holds: the branch keeps the compiler from moving a
       // round's stores into the next round's arithmetic, which costs registers
       if (kx < nxh) {
@@ -412,11 +442,20 @@ __device__ __forceinline__ bool unit_folds(int unit, int C, int R, int nxh, int 
   return um - k2 * nchunk == 0 && (k2 == 0 || k2 == (R >> 1));
 }
 
+// Whether the analysis body runs the wave-level transforms on this shape.
+template <typename T, int L, int VAR>
+constexpr bool k2_wave_fft() { return std::is_same<T, float>::value && L == 128 && VAR != K2V_SPLIT; }
+
 template <typename T, int L, int NMAX, int VAR>
 __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args a) {
   if (VAR == K2V_SPLIT || unit_folds(blockIdx.x, a.C, a.R, a.nx >> 1, a.group_xcd))
     k2_body<T, L, NMAX, VAR, true>(a, blockIdx.x);
-  else
+  else if constexpr (k2_wave_fft<T, L, VAR>()) {
+    if (a.C == 8)
+      k2_body<T, L, NMAX, VAR, false, true>(a, blockIdx.x);
+    else
+      k2_body<T, L, NMAX, VAR, false>(a, blockIdx.x);
+  } else
     k2_body<T, L, NMAX, VAR, false>(a, blockIdx.x);
 }
 
@@ -433,7 +472,12 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral_batch(const 
   a.key1 = f.key1;
   if (unit_folds(blockIdx.x, a.C, a.R, a.nx >> 1, a.group_xcd))
     k2_body<T, L, NMAX, K2V_PLAIN, true>(a, blockIdx.x);
-  else
+  else if constexpr (k2_wave_fft<T, L, K2V_PLAIN>()) {
+    if (a.C == 8)
+      k2_body<T, L, NMAX, K2V_PLAIN, false, true>(a, blockIdx.x);
+    else
+      k2_body<T, L, NMAX, K2V_PLAIN, false>(a, blockIdx.x);
+  } else
     k2_body<T, L, NMAX, K2V_PLAIN, false>(a, blockIdx.x);
 }
 
