@@ -12,7 +12,10 @@
 // on the y1 positions the thread loaded, which it overwrites in place.  The
 // exchanges between passes go through two LDS buffers in turn (one block
 // synchronisation each); every field's loads are issued before any transform,
-// and each inverse round first draws and applies its members' update.
+// and each inverse round first draws and applies its members' update.  Float32
+// analysis units of eight length-128 columns transform with wave_fft.hpp
+// instead (one exchange per transform), which leaves point i of a thread at
+// bin k1 = wave_fft128_bin(t2, i).
 //
 // The unit geometry (XCD grouping) and the folded kx = 0 column, whose packed
 // rows a fold unit splits after its forward transforms and joins before its
@@ -173,16 +176,13 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   const V2<T>* const tw = copy_twiddles<T, L>(lds0 + 2 * FB * SEQP, tab);
   V2<T>* const xch = lds0 + 2 * FB * SEQP + L;  // two buffers of FB x L, used in turn
   int xpar = 0;
-  WaveFft128 wf;
-  if constexpr (WF) {
-    lds_barrier();  // the twiddle copy, read by every thread before any exchange
-    wf.init(reinterpret_cast<const V2<float>*>(tw), t2);
-  }
+  if constexpr (WF) lds_barrier();  // the twiddle copy, read before the first exchange
+  const V2<float>* const twf = reinterpret_cast<const V2<float>*>(tw);
   // the length-L transforms of FB2 fields through the current exchange buffer
   auto fwd = [&](auto& blk) __attribute__((always_inline)) {
     constexpr int FB2 = sizeof(blk) / sizeof(blk[0]);
     if constexpr (WF) {
-      wave_fft128_forward<FB2>(blk, wf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
+      wave_fft128_forward<FB2>(blk, twf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
       lp.parity ^= 1;
     } else {
       fft_forward<T, L, P, FB2, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
@@ -191,7 +191,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   auto inv = [&](auto& blk) __attribute__((always_inline)) {
     constexpr int FB2 = sizeof(blk) / sizeof(blk[0]);
     if constexpr (WF) {
-      wave_fft128_inverse<FB2>(blk, wf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
+      wave_fft128_inverse<FB2>(blk, twf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
       lp.parity ^= 1;
     } else {
       fft_inverse<T, L, P, FB2, SEQP, false, Lay, L>(blk, t2, lp, C, tw);

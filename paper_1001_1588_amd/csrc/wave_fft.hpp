@@ -41,33 +41,29 @@ __device__ __forceinline__ void idft4(cx<float>& v0, cx<float>& v1, cx<float>& v
 // Exchange register bit 0 with lane bit 4 (pairs 0-1 and 2-3) and register bit
 // 1 with lane bit 5 (pairs 0-2 and 1-3): afterwards the value at lane bits
 // (b4, b5), register (r0, r1) is the one that was at lane bits (r0, r1),
-// register (b4, b5).  Each swap is its own inverse and the two commute.
-// v_permlane16_swap_b32 a, b exchanges the odd rows of 16 lanes of a with the
-// even rows of b, v_permlane32_swap_b32 the upper 32 lanes of a with the lower
-// 32 of b, both registers in place.  They are written as inline assembly with
-// both operands read and written: the compiler's own builtin for them has
-// folded the second result into the first.  The s_nop before each covers the
-// wait states after a VALU write of an operand, the one after the hazard of a
-// following VALU read.
-__device__ __forceinline__ void swap16(float& a, float& b) {
-  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
-}
-__device__ __forceinline__ void swap32(float& a, float& b) {
-  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
-}
-__device__ __forceinline__ void swap16(cx<float>& a, cx<float>& b) {
-  swap16(a.re, b.re);
-  swap16(a.im, b.im);
-}
-__device__ __forceinline__ void swap32(cx<float>& a, cx<float>& b) {
-  swap32(a.re, b.re);
-  swap32(a.im, b.im);
-}
+// register (b4, b5).  v_permlane16_swap_b32 a, b exchanges the odd rows of 16
+// lanes of a with the even rows of b, v_permlane32_swap_b32 the upper 32 lanes
+// of a with the lower 32 of b, both registers in place.  They are written as
+// inline assembly with every operand read and written (the compiler's builtin
+// for them has folded the second result into the first), and the s_nop
+// instructions give the wait states at each dependence: after the VALU writes
+// of the operands, between the two swap steps (the second reads the first's
+// results) and before the VALU reads that follow.
 __device__ __forceinline__ void swap_lane45(cx<float> (&v)[4]) {
-  swap16(v[0], v[1]);
-  swap16(v[2], v[3]);
-  swap32(v[0], v[2]);
-  swap32(v[1], v[3]);
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_permlane16_swap_b32 %0, %2\n\t"
+      "v_permlane16_swap_b32 %1, %3\n\t"
+      "v_permlane16_swap_b32 %4, %6\n\t"
+      "v_permlane16_swap_b32 %5, %7\n\t"
+      "s_nop 1\n\t"
+      "v_permlane32_swap_b32 %0, %4\n\t"
+      "v_permlane32_swap_b32 %1, %5\n\t"
+      "v_permlane32_swap_b32 %2, %6\n\t"
+      "v_permlane32_swap_b32 %3, %7\n\t"
+      "s_nop 1"
+      : "+v"(v[0].re), "+v"(v[0].im), "+v"(v[1].re), "+v"(v[1].im), "+v"(v[2].re), "+v"(v[2].im), "+v"(v[3].re),
+        "+v"(v[3].im));
 }
 
 // The value of lane l ^ 8 (a rotation by 8 within each row of 16 lanes).
@@ -99,19 +95,22 @@ __device__ __forceinline__ void twiddle8(cx<float> (&v)[4], bool odd) {
 
 }  // namespace wfft
 
-// The thread's twiddles W_128^k from the block's LDS copy tw of W_128^k, k < 128.
-struct WaveFft128 {
-  cx<float> w1a, w2a;  // W_128^t2, W_128^(2 t2) (step 1; W^(3 t2) formed as their product)
-  cx<float> w1b, w2b;  // W_32^l, W_32^(2 l), l = t2 mod 8 (step 2)
-  float sgn;           // +1 where lane bit 3 is clear, else -1
+// The thread's twiddles, read from the block's LDS copy tw of W_128^k (k < 128)
+// at each transform rather than held across the sweep: W_128^t2, W_128^(2 t2)
+// (step 1) and W_32^l, W_32^(2 l), l = t2 mod 8 (step 2); the third power of
+// each is their product.
+struct WaveTw {
+  cx<float> w1a, w2a, w3a, w1b, w2b, w3b;
+  float sgn;  // +1 where lane bit 3 is clear, else -1
   bool odd;
-
-  __device__ __forceinline__ void init(const V2<float>* tw, int t2) {
+  __device__ __forceinline__ WaveTw(const V2<float>* tw, int t2) {
     w1a = from2<float>(tw[t2]);
     w2a = from2<float>(tw[2 * t2]);
     const int l = t2 & 7;
     w1b = from2<float>(tw[4 * l]);
     w2b = from2<float>(tw[8 * l]);
+    w3a = w1a * w2a;
+    w3b = w1b * w2b;
     odd = (t2 & 1) != 0;
     sgn = odd ? -1.0f : 1.0f;
   }
@@ -119,18 +118,20 @@ struct WaveFft128 {
 
 // NB sequences, v[s][i] = element t2 + 32 i of sequence s in, frequency
 // wave_fft128_bin(t2, i) out.  xbuf: NB x 4 x 32 x C elements of LDS, the
-// thread's column c; every thread of the block calls it (one LDS barrier).
+// thread's column c; tw: the block's W_128^k, visible to every thread (written
+// before an earlier block synchronisation).  Every thread of the block calls
+// it (one LDS barrier).
 template <int NB>
-__device__ __forceinline__ void wave_fft128_forward(cx<float> (&v)[NB][4], const WaveFft128& w, V2<float>* xbuf, int t2,
+__device__ __forceinline__ void wave_fft128_forward(cx<float> (&v)[NB][4], const V2<float>* tw, V2<float>* xbuf, int t2,
                                                     int c) {
   constexpr int C = 8;
-  const cx<float> w3a = w.w1a * w.w2a, w3b = w.w1b * w.w2b;
+  const WaveTw w(tw, t2);
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
     dft4(v[s][0], v[s][1], v[s][2], v[s][3]);
     v[s][1] = v[s][1] * w.w1a;
     v[s][2] = v[s][2] * w.w2a;
-    v[s][3] = v[s][3] * w3a;
+    v[s][3] = v[s][3] * w.w3a;
   }
   // register digit p to the wave: slot (p, n') of sequence s
 #pragma unroll
@@ -148,7 +149,7 @@ __device__ __forceinline__ void wave_fft128_forward(cx<float> (&v)[NB][4], const
     dft4(v[s][0], v[s][1], v[s][2], v[s][3]);
     v[s][1] = v[s][1] * w.w1b;
     v[s][2] = v[s][2] * w.w2b;
-    v[s][3] = v[s][3] * w3b;
+    v[s][3] = v[s][3] * w.w3b;
     wfft::swap_lane45(v[s]);
     dft4(v[s][0], v[s][1], v[s][2], v[s][3]);
     wfft::twiddle8<false>(v[s], w.odd);
@@ -159,10 +160,10 @@ __device__ __forceinline__ void wave_fft128_forward(cx<float> (&v)[NB][4], const
 
 // The inverse: frequencies wave_fft128_bin(t2, i) in, 128 x element t2 + 32 i out.
 template <int NB>
-__device__ __forceinline__ void wave_fft128_inverse(cx<float> (&v)[NB][4], const WaveFft128& w, V2<float>* xbuf, int t2,
+__device__ __forceinline__ void wave_fft128_inverse(cx<float> (&v)[NB][4], const V2<float>* tw, V2<float>* xbuf, int t2,
                                                     int c) {
   constexpr int C = 8;
-  const cx<float> w3a = w.w1a * w.w2a, w3b = w.w1b * w.w2b;
+  const WaveTw w(tw, t2);
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
 #pragma unroll
@@ -172,7 +173,7 @@ __device__ __forceinline__ void wave_fft128_inverse(cx<float> (&v)[NB][4], const
     wfft::swap_lane45(v[s]);
     v[s][1] = v[s][1] * conj(w.w1b);
     v[s][2] = v[s][2] * conj(w.w2b);
-    v[s][3] = v[s][3] * conj(w3b);
+    v[s][3] = v[s][3] * conj(w.w3b);
     wfft::idft4(v[s][0], v[s][1], v[s][2], v[s][3]);
   }
   const int wv = t2 >> 3, l = t2 & 7;
@@ -189,7 +190,7 @@ __device__ __forceinline__ void wave_fft128_inverse(cx<float> (&v)[NB][4], const
   for (int s = 0; s < NB; ++s) {
     v[s][1] = v[s][1] * conj(w.w1a);
     v[s][2] = v[s][2] * conj(w.w2a);
-    v[s][3] = v[s][3] * conj(w3a);
+    v[s][3] = v[s][3] * conj(w.w3a);
     wfft::idft4(v[s][0], v[s][1], v[s][2], v[s][3]);
   }
 }

@@ -121,6 +121,7 @@ Sweeps 1 and 3 read and write the fields through the sine reordering (`true` in 
     for name, text in out.items():
         open(os.path.join(outdir, name), 'w').write(text)
     rows = [k for k in s['kernels'] if '_batch<' in k['name']]
+    graph_ms = float(bj.get('batch', {}).get('graph_ms_per_batch', float('nan')))
     lines = []; tot_us = 0; tot_b = 0
     for k in sorted(rows, key=lambda k: (k['name'], k['grid'])):
         fb, wb = k.get('fetch_bytes'), k.get('write_bytes')
@@ -141,7 +142,7 @@ Workload: 256 filters, square sides drawn uniformly from {{64, 128, 256, 512, 10
 |---|---|---|---|---|---|---|---|---|
 ''' + "\n".join(lines) + f'''
 
-One batch is the sum of one call of each row: {tot_us/1e3:.2f} ms of kernel time.  Rows without counters (`-`) are launches whose grid differed between the counter runs and the trace run (the autotuner's choice of tile rows can differ between runs); their time is included.
+Each launch chain (one grid size, up to 40 filters: sweeps 1, 2 and 3) runs on one of up to three streams forked from the caller's, so the chains overlap on the GPU and each launch's duration includes the time it shares the GPU with the others: one call of each row sums to {tot_us/1e3:.2f} ms of kernel time, against {graph_ms:.2f} ms of wall time per replayed batch (bench.py's graph_ms_per_batch in the same run).  Rows without counters (`-`) are launches whose grid differed between the counter runs and the trace run (the autotuner's choice of tile rows can differ between runs); their time is included.
 '''
     open(os.path.join(outdir, 'batch256_uneven_n16.md'), 'w').write(text)
 
