@@ -90,6 +90,10 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
   constexpr int SEQP = Lay::elems(L);
   static_assert(L >= k11_min_L && CH >= 1 && CH <= 32, "mirror lanes must share a wave");
   static_assert(NMAX % 4 == 0 && NMAX % FB == 0, "member bucket");
+  // float32 length-128 transforms in the wave (wave_fft.hpp: eight columns, the
+  // bins of a thread at wave_fft128_bin); the mirror lanes hold the same
+  // permutation, so a bin's mirror stays in the lane CH to the right
+  constexpr bool WF = std::is_same<T, float>::value && L == 128 && C == 8;
   extern __shared__ unsigned char k11_lds_raw[];
 
   const V2<T>* __restrict__ tab = static_cast<const V2<T>*>(a.tab);
@@ -143,7 +147,7 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
   // (formed where used rather than kept in registers)
   const int n1 = ny, n2 = nx;
   auto kr_at = [&](int i) __attribute__((always_inline)) -> int {
-    const int k1 = t2 + TF2 * i;
+    const int k1 = WF ? wave_fft128_bin(t2, i) : t2 + TF2 * i;
     const int kyA = k2 + R * k1;
     if (!col0) return hb ? (n1 - kyA) & (n1 - 1) : kyA;
     if (self) return kyA;                           // the split gives a the kx = 0 bin, b the kx = nx/2 bin
@@ -191,6 +195,16 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
   cx<T> wpf[P], wmf[P];
   phase_w(wpf, wmf);
   lds_barrier();  // the LDS twiddles are visible
+  auto fwd = [&](auto& blk) __attribute__((always_inline)) {
+    constexpr int FB2 = sizeof(blk) / sizeof(blk[0]);
+    if constexpr (WF) {
+      wave_fft128_forward<FB2>(blk, reinterpret_cast<const V2<float>*>(tw),
+                               reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
+      lp.parity ^= 1;
+    } else {
+      fft_forward<T, L, P, FB2, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+    }
+  };
   static_for<0, NMAX, FB>([&](auto F0) __attribute__((always_inline)) {
     constexpr int f0 = decltype(F0)::value;
     if (f0 < N) {
@@ -201,7 +215,7 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
 #pragma unroll
         for (int b = 0; b < FB; ++b) blk[b][i] = u[f0 + b][i] * t;
       }
-      fft_forward<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+      fwd(blk);
 #pragma unroll
       for (int b = 0; b < FB; ++b)
 #pragma unroll
@@ -212,7 +226,7 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
     cx<T> dv[1][P];
 #pragma unroll
     for (int i = 0; i < P; ++i) dv[0][i] = u[NMAX][i] * tw_y(i);
-    fft_forward<T, L, P, 1, SEQP, false, Lay, L>(dv, t2, lp, C, tw);
+    fwd(dv);
 #pragma unroll
     for (int i = 0; i < P; ++i) u[NMAX][i] = to_x(i, dv[0][i], lane_xor(dv[0][i], CH), wpf, wmf);
   }
@@ -313,7 +327,13 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
             v = send;
           blk[b][i] = v;
         }
-      fft_inverse<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+      if constexpr (WF) {
+        wave_fft128_inverse<FB>(blk, reinterpret_cast<const V2<float>*>(tw),
+                                reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
+        lp.parity ^= 1;
+      } else {
+        fft_inverse<T, L, P, FB, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
+      }
       if (stores) {
 #pragma unroll
         for (int b = 0; b < FB; ++b)
