@@ -62,6 +62,32 @@ def test_config_multiblock_1024_n10_m4():
         assert rel_l2(got[:, j], ref[:, j]) <= 1e-5
 
 
+def test_large_block_offsets_centred_cross_covariance():
+    """Every block carries a constant offset of 300 times its spread (data
+    offset with block 0).  Eq. (7) centres both factors; a kernel that summed
+    the raw coefficients against the observed deviations would rely on those
+    deviations summing to exactly zero, which float32 leaves at about N eps
+    times the mean, and the DC gain of every unobserved block would be off by
+    roughly 1e-2.  The increments out - ens are compared, overall and in their
+    DC (grid mean) component per member and block, against the oracle's.  The
+    float32 transforms of fields whose norm is 300 times their spread carry
+    errors of order eps log2(n) 300 ~ 1e-4 of the spread, hence 1e-3."""
+    ny = nx = 64
+    N, Ls = 6, (2.0, 4.0, 8.0)
+    tw = twin.make_multiblock_twin(ny, nx, N, seed=31, Ls=Ls, dtype=np.float32)
+    offs = np.array([300.0, -450.0, 600.0]) * tw.ens.std(axis=(0, 2, 3))
+    ens = (tw.ens.astype(np.float64) + offs[None, :, None, None]).astype(np.float32)
+    data = (tw.data.astype(np.float64) + offs[0]).astype(np.float32)
+    out = _lib.analyze_multi(dev(ens), dev(data), dev(tw.R_spec), tw.seed)
+    torch.cuda.synchronize()
+    ref = multiblock.analyze_multi(ens, data, tw.R_spec, tw.seed, method="matmul")
+    inc, inc_ref = out.cpu().numpy().astype(np.float64) - ens, ref - ens
+    assert rel_l2(inc, inc_ref) <= 1e-3
+    dc, dc_ref = inc.mean(axis=(2, 3)), inc_ref.mean(axis=(2, 3))
+    scale = np.abs(inc_ref).mean()
+    assert np.abs(dc - dc_ref).max() <= 1e-3 * scale
+
+
 def test_one_block_equals_single_block_analysis():
     tw = twin.random_ensemble(128, 64, 6, seed=5, dtype=np.float32, R_kind="spectral")
     R = dev(tw.R_spec)
