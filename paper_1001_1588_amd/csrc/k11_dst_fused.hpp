@@ -90,10 +90,10 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
   constexpr int SEQP = Lay::elems(L);
   static_assert(L >= k11_min_L && CH >= 1 && CH <= 32, "mirror lanes must share a wave");
   static_assert(NMAX % 4 == 0 && NMAX % FB == 0, "member bucket");
-  // float32 length-128 transforms in the wave (wave_fft.hpp: eight columns, the
-  // bins of a thread at wave_fft128_bin); the mirror lanes hold the same
-  // permutation, so a bin's mirror stays in the lane CH to the right
-  constexpr bool WF = std::is_same<T, float>::value && L == 128 && C == 8;
+  // float32 length-64 and length-128 transforms in the wave (wave_fft.hpp:
+  // 1024 / L columns, the bins of a thread at wave_fft_bin); the mirror lanes
+  // hold the same permutation, so a bin's mirror stays in the lane CH away
+  constexpr bool WF = std::is_same<T, float>::value && wave_fft_length<L>() && C == 1024 / L;
   extern __shared__ unsigned char k11_lds_raw[];
 
   const V2<T>* __restrict__ tab = static_cast<const V2<T>*>(a.tab);
@@ -147,7 +147,7 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
   // (formed where used rather than kept in registers)
   const int n1 = ny, n2 = nx;
   auto kr_at = [&](int i) __attribute__((always_inline)) -> int {
-    const int k1 = WF ? wave_fft128_bin(t2, i) : t2 + TF2 * i;
+    const int k1 = WF ? wave_fft_bin<L>(t2, i) : t2 + TF2 * i;
     const int kyA = k2 + R * k1;
     if (!col0) return hb ? (n1 - kyA) & (n1 - 1) : kyA;
     if (self) return kyA;                           // the split gives a the kx = 0 bin, b the kx = nx/2 bin
@@ -198,7 +198,7 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
   auto fwd = [&](auto& blk) __attribute__((always_inline)) {
     constexpr int FB2 = sizeof(blk) / sizeof(blk[0]);
     if constexpr (WF) {
-      wave_fft128_forward<FB2>(blk, reinterpret_cast<const V2<float>*>(tw),
+      wave_fft_forward<L, FB2>(blk, reinterpret_cast<const V2<float>*>(tw),
                                reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
       lp.parity ^= 1;
     } else {
@@ -328,7 +328,7 @@ __device__ __forceinline__ void k11_body(const K9Args& a, int k2, int q) {
           blk[b][i] = v;
         }
       if constexpr (WF) {
-        wave_fft128_inverse<FB>(blk, reinterpret_cast<const V2<float>*>(tw),
+        wave_fft_inverse<L, FB>(blk, reinterpret_cast<const V2<float>*>(tw),
                                 reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
         lp.parity ^= 1;
       } else {

@@ -13,9 +13,9 @@
 // exchanges between passes go through two LDS buffers in turn (one block
 // synchronisation each); every field's loads are issued before any transform,
 // and each inverse round first draws and applies its members' update.  Float32
-// analysis units of eight length-128 columns transform with wave_fft.hpp
-// instead (one exchange per transform), which leaves point i of a thread at
-// bin k1 = wave_fft128_bin(t2, i).
+// analysis units of length-64 or length-128 columns (16 or 8 of them)
+// transform with wave_fft.hpp instead (one exchange per transform), which
+// leaves point i of a thread at bin k1 = wave_fft_bin<L>(t2, i).
 //
 // The unit geometry (XCD grouping) and the folded kx = 0 column, whose packed
 // rows a fold unit splits after its forward transforms and joins before its
@@ -133,13 +133,13 @@ enum { K2V_PLAIN = 0, K2V_LAM = 1, K2V_SPLIT = 2 };
 // carry the split and join of packed rows and the pair slots (needed only by
 // the units with g.fold); the analysis kernels run the body without them in
 // every other unit, which keeps its registers to the common case.  WF: the
-// length-128 transforms of wave_fft.hpp (float32 units of eight columns
-// without a packed column), whose bins sit at wave_fft128_bin rather than in
-// natural order; loads and stores are the same.
+// transforms of wave_fft.hpp (float32 units of 1024 / L columns without a
+// packed column, L = 64 or 128), whose bins sit at wave_fft_bin rather than
+// in natural order; loads and stores are the same.
 template <typename T, int L, int NMAX, int VAR, bool FOLD = true, bool WF = false>
 __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
-  static_assert(!WF || (L == 128 && !FOLD && VAR != K2V_SPLIT && std::is_same<T, float>::value),
-                "the wave-level transform serves float32 analysis units of length 128");
+  static_assert(!WF || (wave_fft_length<L>() && !FOLD && VAR != K2V_SPLIT && std::is_same<T, float>::value),
+                "the wave-level transform serves float32 analysis units of length 64 or 128");
   constexpr bool SPLIT = VAR == K2V_SPLIT;
   const void* const lam_map = VAR == K2V_PLAIN ? nullptr : a.lam_map;
   constexpr int P = k2_points(L);
@@ -182,7 +182,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   auto fwd = [&](auto& blk) __attribute__((always_inline)) {
     constexpr int FB2 = sizeof(blk) / sizeof(blk[0]);
     if constexpr (WF) {
-      wave_fft128_forward<FB2>(blk, twf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
+      wave_fft_forward<L, FB2>(blk, twf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
       lp.parity ^= 1;
     } else {
       fft_forward<T, L, P, FB2, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
@@ -191,7 +191,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   auto inv = [&](auto& blk) __attribute__((always_inline)) {
     constexpr int FB2 = sizeof(blk) / sizeof(blk[0]);
     if constexpr (WF) {
-      wave_fft128_inverse<FB2>(blk, twf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
+      wave_fft_inverse<L, FB2>(blk, twf, reinterpret_cast<V2<float>*>(lp.parity ? lp.buf1 : lp.buf0), t2, c);
       lp.parity ^= 1;
     } else {
       fft_inverse<T, L, P, FB2, SEQP, false, Lay, L>(blk, t2, lp, C, tw);
@@ -257,7 +257,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   T csum = T(0);
 #pragma unroll
   for (int i = 0; i < P; ++i) {
-    const int r = WF ? wave_fft128_bin(t2, i) : t2 + TF2 * i;
+    const int r = WF ? wave_fft_bin<L>(t2, i) : t2 + TF2 * i;
     const int ky = cb.kyb + R * r, kxb = FOLD ? (r > cb.thr ? nxh : kx) : kxt;
     const bool pr = FOLD && (i == 0 ? cb.pair0 : (i == P / 2 ? cb.pairh : false));
     const size_t bin = (size_t)ky * nh + kxb, bin_n = (size_t)ky * nh + nxh;
@@ -444,14 +444,14 @@ __device__ __forceinline__ bool unit_folds(int unit, int C, int R, int nxh, int 
 
 // Whether the analysis body runs the wave-level transforms on this shape.
 template <typename T, int L, int VAR>
-constexpr bool k2_wave_fft() { return std::is_same<T, float>::value && L == 128 && VAR != K2V_SPLIT; }
+constexpr bool k2_wave_fft() { return std::is_same<T, float>::value && wave_fft_length<L>() && VAR != K2V_SPLIT; }
 
 template <typename T, int L, int NMAX, int VAR>
 __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral(const K2Args a) {
   if (VAR == K2V_SPLIT || unit_folds(blockIdx.x, a.C, a.R, a.nx >> 1, a.group_xcd))
     k2_body<T, L, NMAX, VAR, true>(a, blockIdx.x);
   else if constexpr (k2_wave_fft<T, L, VAR>()) {
-    if (a.C == 8)
+    if (a.C == 1024 / L)
       k2_body<T, L, NMAX, VAR, false, true>(a, blockIdx.x);
     else
       k2_body<T, L, NMAX, VAR, false>(a, blockIdx.x);
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(k2_threads_target, 2) void k2_spectral_batch(const 
   if (unit_folds(blockIdx.x, a.C, a.R, a.nx >> 1, a.group_xcd))
     k2_body<T, L, NMAX, K2V_PLAIN, true>(a, blockIdx.x);
   else if constexpr (k2_wave_fft<T, L, K2V_PLAIN>()) {
-    if (a.C == 8)
+    if (a.C == 1024 / L)
       k2_body<T, L, NMAX, K2V_PLAIN, false, true>(a, blockIdx.x);
     else
       k2_body<T, L, NMAX, K2V_PLAIN, false>(a, blockIdx.x);

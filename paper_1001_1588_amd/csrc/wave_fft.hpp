@@ -1,31 +1,41 @@
-// Length-128 transforms of the spectral sweep with one block exchange.
+// Length-64 and length-128 transforms of the spectral sweep with one block
+// exchange.
 //
-// The sweep's thread (c, t2) = (tid % 8, tid / 8) of a 256-thread block holds
-// elements n = t2 + 32 i (i < 4) of a column: the two top bits of n are the
-// register index i, the next two the wave (t2 / 8) and the three low bits the
-// lane bits 3..5.  The forward transform is a decimation in frequency, digit by
-// digit, each radix-4 (or 2) step on the digit that sits in registers:
-//   1. radix 4 over i, twiddle W_128^(t2 p);
+// The sweep's thread (c, t2) = (tid % C, tid / C) of a 256-thread block holds
+// elements n = t2 + (L/4) i (i < 4) of a column, C = 1024 / L columns (8 at
+// L = 128, 16 at L = 64): the two top bits of n are the register index i, the
+// next two the wave (t2 / (64 / C)), and the low bits (three at L = 128, two at
+// L = 64) lane bits 3..5 or 4..5.  The forward transform is a decimation in
+// frequency, digit by digit, each radix-4 (or 2) step on the digit that sits in
+// registers:
+//   1. radix 4 over i, twiddle W_L^(t2 p);
 //   2. LDS transpose of the register digit with the wave digit, radix 4, twiddle
-//      W_32^(l p) with l = t2 mod 8;
+//      W_(L/4)^(l p) with l the lane part of t2;
 //   3. v_permlane16_swap / v_permlane32_swap exchange the register digit with
-//      lane bits 4 and 5, radix 4, twiddle W_8^(n0 p), n0 = lane bit 3;
-//   4. radix 2 across lane bit 3 (the partner's value by a DPP row rotation).
-// X[k] then sits at k = p1 + 4 p2 + 16 p3 + 64 s: p1 the wave, p2 lane bits 4
-// and 5, p3 the register index and s lane bit 3 (wave_fft128_bin).  The inverse
-// runs the same steps backwards with conjugate twiddles and returns x * 128 in
-// the natural order, so loads and stores stay those of the Stockham form.  One
-// block synchronisation per transform instead of three, and two fewer LDS round
-// trips.
+//      lane bits 4 and 5, radix 4 (at L = 128 with twiddle W_8^(n0 p), n0 =
+//      lane bit 3);
+//   4. (L = 128) radix 2 across lane bit 3, the partner's value by a DPP row
+//      rotation.
+// X[k] then sits at k = p1 + 4 p2 + 16 p3 (+ 64 s at L = 128): p1 the wave, p2
+// lane bits 4 and 5, p3 the register index and s lane bit 3 (wave_fft_bin).
+// The inverse runs the same steps backwards with conjugate twiddles and returns
+// x * L in the natural order, so loads and stores stay those of the Stockham
+// form.  One block synchronisation per transform instead of three (L = 128) or
+// two (L = 64).
 #pragma once
 
 #include "fft_core.hpp"
 
 namespace fftenkf {
 
-// The frequency held by register i of the thread with row index t2.
-__host__ __device__ __forceinline__ int wave_fft128_bin(int t2, int i) {
-  return (t2 >> 3) + 4 * ((t2 >> 1) & 3) + 16 * i + 64 * (t2 & 1);
+// Lengths served, and the frequency held by register i of the thread with row
+// index t2.
+template <int L>
+constexpr bool wave_fft_length() { return L == 64 || L == 128; }
+template <int L>
+__host__ __device__ __forceinline__ int wave_fft_bin(int t2, int i) {
+  if constexpr (L == 128) return (t2 >> 3) + 4 * ((t2 >> 1) & 3) + 16 * i + 64 * (t2 & 1);
+  else return (t2 >> 2) + 4 * (t2 & 3) + 16 * i;
 }
 
 namespace wfft {
@@ -95,18 +105,20 @@ __device__ __forceinline__ void twiddle8(cx<float> (&v)[4], bool odd) {
 
 }  // namespace wfft
 
-// The thread's twiddles, read from the block's LDS copy tw of W_128^k (k < 128)
-// at each transform rather than held across the sweep: W_128^t2, W_128^(2 t2)
-// (step 1) and W_32^l, W_32^(2 l), l = t2 mod 8 (step 2); the third power of
-// each is their product.
+// The thread's twiddles, read from the block's LDS copy tw of W_L^k (k < L) at
+// each transform rather than held across the sweep: W_L^t2, W_L^(2 t2) (step 1)
+// and W_(L/4)^l, W_(L/4)^(2 l) (step 2); the third power of each is their
+// product.
+template <int L>
 struct WaveTw {
+  static constexpr int LB = L / 16;  // values of the lane part l of t2
   cx<float> w1a, w2a, w3a, w1b, w2b, w3b;
-  float sgn;  // +1 where lane bit 3 is clear, else -1
+  float sgn;  // L = 128: +1 where lane bit 3 is clear, else -1
   bool odd;
   __device__ __forceinline__ WaveTw(const V2<float>* tw, int t2) {
     w1a = from2<float>(tw[t2]);
     w2a = from2<float>(tw[2 * t2]);
-    const int l = t2 & 7;
+    const int l = t2 & (LB - 1);
     w1b = from2<float>(tw[4 * l]);
     w2b = from2<float>(tw[8 * l]);
     w3a = w1a * w2a;
@@ -116,16 +128,17 @@ struct WaveTw {
   }
 };
 
-// NB sequences, v[s][i] = element t2 + 32 i of sequence s in, frequency
-// wave_fft128_bin(t2, i) out.  xbuf: NB x 4 x 32 x C elements of LDS, the
-// thread's column c; tw: the block's W_128^k, visible to every thread (written
+// NB sequences, v[s][i] = element t2 + (L/4) i of sequence s in, frequency
+// wave_fft_bin<L>(t2, i) out.  xbuf: NB x 4 x (L/4) x C elements of LDS, the
+// thread's column c; tw: the block's W_L^k, visible to every thread (written
 // before an earlier block synchronisation).  Every thread of the block calls
 // it (one LDS barrier).
-template <int NB>
-__device__ __forceinline__ void wave_fft128_forward(cx<float> (&v)[NB][4], const V2<float>* tw, V2<float>* xbuf, int t2,
-                                                    int c) {
-  constexpr int C = 8;
-  const WaveTw w(tw, t2);
+template <int L, int NB>
+__device__ __forceinline__ void wave_fft_forward(cx<float> (&v)[NB][4], const V2<float>* tw, V2<float>* xbuf, int t2,
+                                                 int c) {
+  static_assert(wave_fft_length<L>(), "wave-level transform lengths: 64 and 128");
+  constexpr int C = 1024 / L, Q = L / 4, LB = L / 16;
+  const WaveTw<L> w(tw, t2);
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
     dft4(v[s][0], v[s][1], v[s][2], v[s][3]);
@@ -137,13 +150,13 @@ __device__ __forceinline__ void wave_fft128_forward(cx<float> (&v)[NB][4], const
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll
-    for (int p = 0; p < 4; ++p) xbuf[((s * 4 + p) * 32 + t2) * C + c] = to2<float>(v[s][p]);
+    for (int p = 0; p < 4; ++p) xbuf[((s * 4 + p) * Q + t2) * C + c] = to2<float>(v[s][p]);
   lds_barrier();
-  const int wv = t2 >> 3, l = t2 & 7;
+  const int wv = t2 / LB, l = t2 & (LB - 1);
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[s][q] = from2<float>(xbuf[((s * 4 + wv) * 32 + l + 8 * q) * C + c]);
+    for (int q = 0; q < 4; ++q) v[s][q] = from2<float>(xbuf[((s * 4 + wv) * Q + l + LB * q) * C + c]);
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
     dft4(v[s][0], v[s][1], v[s][2], v[s][3]);
@@ -152,23 +165,28 @@ __device__ __forceinline__ void wave_fft128_forward(cx<float> (&v)[NB][4], const
     v[s][3] = v[s][3] * w.w3b;
     wfft::swap_lane45(v[s]);
     dft4(v[s][0], v[s][1], v[s][2], v[s][3]);
-    wfft::twiddle8<false>(v[s], w.odd);
+    if constexpr (L == 128) {
+      wfft::twiddle8<false>(v[s], w.odd);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[s][i] = wfft::radix2_lane8(v[s][i], w.sgn);
+      for (int i = 0; i < 4; ++i) v[s][i] = wfft::radix2_lane8(v[s][i], w.sgn);
+    }
   }
 }
 
-// The inverse: frequencies wave_fft128_bin(t2, i) in, 128 x element t2 + 32 i out.
-template <int NB>
-__device__ __forceinline__ void wave_fft128_inverse(cx<float> (&v)[NB][4], const V2<float>* tw, V2<float>* xbuf, int t2,
-                                                    int c) {
-  constexpr int C = 8;
-  const WaveTw w(tw, t2);
+// The inverse: frequencies wave_fft_bin<L>(t2, i) in, L x element t2 + (L/4) i out.
+template <int L, int NB>
+__device__ __forceinline__ void wave_fft_inverse(cx<float> (&v)[NB][4], const V2<float>* tw, V2<float>* xbuf, int t2,
+                                                 int c) {
+  static_assert(wave_fft_length<L>(), "wave-level transform lengths: 64 and 128");
+  constexpr int C = 1024 / L, Q = L / 4, LB = L / 16;
+  const WaveTw<L> w(tw, t2);
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
+    if constexpr (L == 128) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[s][i] = wfft::radix2_lane8(v[s][i], w.sgn);
-    wfft::twiddle8<true>(v[s], w.odd);
+      for (int i = 0; i < 4; ++i) v[s][i] = wfft::radix2_lane8(v[s][i], w.sgn);
+      wfft::twiddle8<true>(v[s], w.odd);
+    }
     wfft::idft4(v[s][0], v[s][1], v[s][2], v[s][3]);
     wfft::swap_lane45(v[s]);
     v[s][1] = v[s][1] * conj(w.w1b);
@@ -176,16 +194,16 @@ __device__ __forceinline__ void wave_fft128_inverse(cx<float> (&v)[NB][4], const
     v[s][3] = v[s][3] * conj(w.w3b);
     wfft::idft4(v[s][0], v[s][1], v[s][2], v[s][3]);
   }
-  const int wv = t2 >> 3, l = t2 & 7;
+  const int wv = t2 / LB, l = t2 & (LB - 1);
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) xbuf[((s * 4 + wv) * 32 + l + 8 * q) * C + c] = to2<float>(v[s][q]);
+    for (int q = 0; q < 4; ++q) xbuf[((s * 4 + wv) * Q + l + LB * q) * C + c] = to2<float>(v[s][q]);
   lds_barrier();
 #pragma unroll
   for (int s = 0; s < NB; ++s)
 #pragma unroll
-    for (int p = 0; p < 4; ++p) v[s][p] = from2<float>(xbuf[((s * 4 + p) * 32 + t2) * C + c]);
+    for (int p = 0; p < 4; ++p) v[s][p] = from2<float>(xbuf[((s * 4 + p) * Q + t2) * C + c]);
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
     v[s][1] = v[s][1] * conj(w.w1a);

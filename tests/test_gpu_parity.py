@@ -67,12 +67,14 @@ CASES = [
     (4096, 8, 4, np.float64, "scalar"),
     (4096, 16, 24, np.float32, "spectral"),
     (16, 4096, 8, np.float64, "spectral"),
-    # length-128 columns in float32 (1024 tall, 8-row tiles): the wave-level
-    # transforms in three member buckets, and a grid too narrow for their
-    # eight-column units (the Stockham form then)
+    # length-128 and length-64 columns in float32 (1024 and 512 tall, 8-row
+    # tiles): the wave-level transforms in several member buckets, and grids too
+    # narrow for their 8- and 16-column units (the Stockham form then)
     (1024, 64, 4, np.float32, "scalar"),
     (1024, 16, 9, np.float32, "spectral"),
     (1024, 8, 5, np.float32, "scalar"),
+    (512, 32, 8, np.float32, "spectral"),
+    (512, 16, 6, np.float32, "scalar"),
 ]
 
 
