@@ -79,10 +79,11 @@ def sweep_bytes(N: int, ny: int, nx: int, s: int, rspec_array: bool) -> dict:
     }
 
 
-def profiled_traffic(family: str, live_ms: float):
+def profiled_traffic(family: str, live_ms: float, exclude=()):
     """HBM bytes per launch of a kernel of `family` from the committed rocprofv3
     counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
-    for a plain copy of known size; profile_summary.py).  One kernel serves several
+    for a plain copy of known size; profile_summary.py).  A record matches when
+    its name contains `family` and none of `exclude`.  One kernel serves several
     workloads, so the profiled dispatch whose average duration is closest to the
     live one is taken; None if there is none within 25%, or if the kernel's
     sources changed since the counters were taken."""
@@ -93,7 +94,9 @@ def profiled_traffic(family: str, live_ms: float):
         return None
     best = None
     for rec in json.load(open(path))["kernels"]:
-        if family not in rec["name"] or rec.get("fetch_bytes") is None or rec.get("write_bytes") is None:
+        if family not in rec["name"] or any(x in rec["name"] for x in exclude):
+            continue
+        if rec.get("fetch_bytes") is None or rec.get("write_bytes") is None:
             continue
         h = hashlib.sha256()
         for f in rec.get("sources", []):
@@ -461,8 +464,12 @@ def main() -> int:
     dom = int(np.argmax(avg))
     achieved = b[names[dom]] / (avg[dom] * 1e-3) / 1e9
     # measured HBM bytes of the three sweeps over their summed time (profiled counters)
-    families = ["k1_forward", "k2_spectral", "k3_inverse"]
-    traffic = [profiled_traffic(families[i], float(avg[i])) if args.rspec == "array" else None for i in range(3)]
+    # the periodic single-analysis kernels: not the batched ones (k2_spectral_batch
+    # and the like do not match "k2_spectral<") nor the sine-basis forms of sweeps
+    # 1 and 3 (template argument SINE = true)
+    families = ["k1_forward<", "k2_spectral<", "k3_inverse<"]
+    traffic = [profiled_traffic(families[i], float(avg[i]), exclude=("true>",)) if args.rspec == "array" else None
+               for i in range(3)]
     three_sweep = None
     if all(t is not None for t in traffic):
         span = float(avg.sum())

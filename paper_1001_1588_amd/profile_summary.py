@@ -30,14 +30,15 @@ CSRC = "paper_1001_1588_amd/csrc/"
 COMMON = [CSRC + "fft_core.hpp", CSRC + "kernels.hpp"]
 SOURCES = {
     "k1_forward": COMMON + [CSRC + "k1_forward.hpp"],
-    "k2_spectral": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "k2_spectral.hpp"],
+    "k2_spectral": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "wave_fft.hpp",
+                             CSRC + "k2_spectral.hpp"],
     "k3_inverse": COMMON + [CSRC + "k1_forward.hpp", CSRC + "k3_inverse.hpp"],
-    "k10_observed": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "k2_spectral.hpp",
-                              CSRC + "k10_observed.hpp"],
+    "k10_observed": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "wave_fft.hpp",
+                              CSRC + "k2_spectral.hpp", CSRC + "k10_observed.hpp"],
     "k7_spectral_mlp": [CSRC + "kernels.hpp", CSRC + "k7_spectral_mlp.hip"],
     "dst_": [CSRC + "fft_core.hpp", CSRC + "kernels.hpp", CSRC + "philox.hpp", CSRC + "k9_dst.hip"],
-    "k11_dst_fused": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "k2_spectral.hpp",
-                               CSRC + "k11_dst_fused.hpp"],
+    "k11_dst_fused": COMMON + [CSRC + "philox.hpp", CSRC + "spectral_unit.hpp", CSRC + "wave_fft.hpp",
+                               CSRC + "k2_spectral.hpp", CSRC + "k11_dst_fused.hpp"],
 }
 COPY = "__amd_rocclr_copyBuffer"
 

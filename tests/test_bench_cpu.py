@@ -68,6 +68,26 @@ def test_profiled_traffic_takes_the_nearest_current_record(tmp_path, monkeypatch
     assert bench.profiled_traffic("k2_spectral", 0.195) == 30.0
     # beyond 25% of every current record's duration: no figure
     assert bench.profiled_traffic("k2_spectral", 0.300) is None
+    # excluded substrings drop records however close their duration
+    assert bench.profiled_traffic("k2_spectral", 0.195, exclude=("true>",)) is None
+    assert bench.profiled_traffic("k2_spectral", 0.105, exclude=("true>",)) == 3.0
+
+
+def test_profiled_traffic_family_with_bracket_skips_batched_kernels(tmp_path, monkeypatch):
+    _fake_profiles(tmp_path, [], {"a.hpp": "kernel a"})
+    good = _hash(tmp_path, ["src/a.hpp"])
+    recs = [
+        {"name": "ns::k2_spectral<float, 128, 20, 0>", "avg_ns": 245e3, "fetch_bytes": 300.0, "write_bytes": 400.0,
+         "sources": ["src/a.hpp"], "sources_sha256_16": good},
+        # a batched launch that happens to take about as long
+        {"name": "ns::k2_spectral_batch<float, 128, 16>", "avg_ns": 244e3, "fetch_bytes": 100.0, "write_bytes": 100.0,
+         "sources": ["src/a.hpp"], "sources_sha256_16": good},
+    ]
+    with open(tmp_path / "profiles" / "kernels_traffic.json", "w") as f:
+        json.dump({"kernels": recs}, f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.profiled_traffic("k2_spectral", 0.2437) == 200.0
+    assert bench.profiled_traffic("k2_spectral<", 0.2437) == 700.0
     assert bench.profiled_traffic("k1_forward", 0.150) is None
     assert bench.profiled_traffic("k3_inverse", 0.150) is None
 
