@@ -636,10 +636,17 @@ std::mutex g_side_mu;
 std::map<int, SidePool> g_side;
 
 // The pool of the current device, or nullptr if there is none and one cannot
-// be made now (under capture, or on a creation failure).  g_side_mu held.
+// be made now (under capture, or on a creation failure), or if `stream`
+// belongs to another device than the current one (the chains then stay on
+// `stream`).  g_side_mu held.
 const SidePool* side_pool(hipStream_t stream) {
-  int dev = 0;
+  int dev = 0, sdev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if (stream != nullptr && hipStreamGetDevice(stream, &sdev) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (stream != nullptr && sdev != dev) return nullptr;
   auto it = g_side.find(dev);
   if (it != g_side.end()) return &it->second;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
