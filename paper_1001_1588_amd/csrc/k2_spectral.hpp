@@ -124,10 +124,11 @@ __device__ __forceinline__ cx<T> sample_variance(const cx<T> (&u)[NMAX][P], int 
 }
 
 // Kernel variants: K2V_PLAIN runs K2_ANALYZE without a given spectrum,
-// K2V_LAM K2_ANALYZE with one (lam_map), K2V_SPLIT every other mode (the
-// statistics-only, inverse-only and test-export modes); the analysis kernel
-// carries none of the others' code.
-enum { K2V_PLAIN = 0, K2V_LAM = 1, K2V_SPLIT = 2 };
+// K2V_LAM K2_ANALYZE with one (lam_map), K2V_CHAT K2_CHAT (the statistics pass
+// of the learned analysis: members only, d neither read nor transformed),
+// K2V_SPLIT every other mode (statistics with write-back, inverse-only and the
+// test exports); the analysis kernel carries none of the others' code.
+enum { K2V_PLAIN = 0, K2V_LAM = 1, K2V_SPLIT = 2, K2V_CHAT = 3 };
 
 // The work of one block; `unit` is its index within one analysis.  FOLD:
 // carry the split and join of packed rows and the pair slots (needed only by
@@ -139,9 +140,11 @@ enum { K2V_PLAIN = 0, K2V_LAM = 1, K2V_SPLIT = 2 };
 template <typename T, int L, int NMAX, int VAR, bool FOLD = true, bool WF = false>
 __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   static_assert(!WF || (wave_fft_length<L>() && !FOLD && VAR != K2V_SPLIT && std::is_same<T, float>::value),
-                "the wave-level transform serves float32 analysis units of length 64 or 128");
-  constexpr bool SPLIT = VAR == K2V_SPLIT;
-  const void* const lam_map = VAR == K2V_PLAIN ? nullptr : a.lam_map;
+                "the wave-level transform serves float32 units of length 64 or 128 whose fields are not stored back "
+                "transformed");
+  constexpr bool SPLIT = VAR == K2V_SPLIT || VAR == K2V_CHAT;  // the statistics and export code
+  constexpr bool NEED_D = VAR != K2V_CHAT;
+  const void* const lam_map = (VAR == K2V_LAM || VAR == K2V_SPLIT) ? a.lam_map : nullptr;
   constexpr int P = k2_points(L);
   constexpr int TF2 = L / P;
   constexpr int FB = K2Geom<T>::template fb<NMAX>();
@@ -157,7 +160,7 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
   const int t2 = tid / C;
   const int N = a.N, R = a.R, ny = a.ny;
   const int nxh = a.nx >> 1, nh = nxh + 1;
-  const int mode = SPLIT ? a.mode : K2_ANALYZE;
+  const int mode = VAR == K2V_CHAT ? K2_CHAT : SPLIT ? a.mode : K2_ANALYZE;
 
   // unit geometry; every field is read and written through one buffer
   // resource over the unit's region, with per-thread byte offsets of the P
@@ -212,7 +215,8 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
     }
   });
 #pragma unroll
-  for (int i = 0; i < P; ++i) dv[0][i] = from2<T>(buf_ld<T>(buf, voff[i], (uint32_t)N * fbytes));
+  for (int i = 0; i < P; ++i)
+    dv[0][i] = NEED_D ? from2<T>(buf_ld<T>(buf, voff[i], (uint32_t)N * fbytes)) : cx<T>{T(0), T(0)};
 
   // forward length-L transforms (the inverse-only mode starts from transformed fields)
   if (mode != K2_INVERSE) {
@@ -232,8 +236,10 @@ __device__ __forceinline__ void k2_body(const K2Args& a, int unit) {
           for (int i = 0; i < P; ++i) u[f0 + b][i] = blk[b][i];
       }
     }
-    fwd(dv);
-    if (FOLD && g.fold) fold_exchange<T, 1, FB, P, TF2, L>(dv, xch, xpar, t2, xlane, k2, true);
+    if constexpr (NEED_D) {
+      fwd(dv);
+      if (FOLD && g.fold) fold_exchange<T, 1, FB, P, TF2, L>(dv, xch, xpar, t2, xlane, k2, true);
+    }
   }
 
   // ---- eq. (2) per bin, then the gain g of eq. (3).  The update of a member
@@ -507,6 +513,7 @@ hipError_t launch_k2_variant(const K2Args& a, hipStream_t st) {
 
 template <typename T, int L, int NMAX>
 hipError_t launch_k2_shape(const K2Args& a, hipStream_t st) {
+  if (a.mode == K2_CHAT) return launch_k2_variant<T, L, NMAX, K2V_CHAT>(a, st);
   if (a.mode != K2_ANALYZE) return launch_k2_variant<T, L, NMAX, K2V_SPLIT>(a, st);
   if (a.lam_map != nullptr) return launch_k2_variant<T, L, NMAX, K2V_LAM>(a, st);
   return launch_k2_variant<T, L, NMAX, K2V_PLAIN>(a, st);
