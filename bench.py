@@ -111,7 +111,7 @@ def profiled_traffic(family: str, live_ms: float, exclude=()):
 
 def copy_ceiling(mib: int, hip: HipEvents, reps: int = 10) -> dict:
     """Device-to-device copy of `mib` MiB (read + write counted): the achievable
-    HBM rate on this box, and the reference kernel for scaling byte counters."""
+    HBM rate on this machine, and the reference kernel for scaling byte counters."""
     import torch
 
     src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda:0").fill_(1)

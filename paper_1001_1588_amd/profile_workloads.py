@@ -16,7 +16,7 @@ import os
 
 
 def write(s: dict, bj: dict, outdir: str) -> None:
-    """s: profile_summary's record; bj: one bench.py JSON line of the same box."""
+    """s: profile_summary's record; bj: one bench.py JSON line of the same machine."""
     K = {(k['name'], k['grid']): k for k in s['kernels']}
     def get(name, grid):
         return K[(name, grid)]
@@ -71,7 +71,7 @@ Workload: periodic 2048x2048 grid, N = 20 members, float32, spectrum |k|^-3, R =
 {row(*K2, 21*h + r4 + 20*h)}
 {row(*K3, 20*h + 20*n*4)}
 
-Three-sweep HBM rate on measured bytes: {' + '.join(f"{(k['fetch_bytes']+k['write_bytes'])/1e6:.1f}" for k in tr)} MB over {' + '.join(f"{k['avg_ns']/1e3:.1f}" for k in tr)} us = {tb/(tt*1e-9)/1e12:.2f} TB/s, {tb/(tt*1e-9)/8e12*100:.0f}% of 8 TB/s.  bench.py's 1 GiB device copy runs at {copy_live:.2f} TB/s on the same box without the profiler.  The spectral sweep is the dominant kernel ({tr[1]['avg_ns']/tt*100:.0f}% of the time).
+Three-sweep HBM rate on measured bytes: {' + '.join(f"{(k['fetch_bytes']+k['write_bytes'])/1e6:.1f}" for k in tr)} MB over {' + '.join(f"{k['avg_ns']/1e3:.1f}" for k in tr)} us = {tb/(tt*1e-9)/1e12:.2f} TB/s, {tb/(tt*1e-9)/8e12*100:.0f}% of 8 TB/s.  bench.py's 1 GiB device copy runs at {copy_live:.2f} TB/s on the same machine without the profiler.  The spectral sweep is the dominant kernel ({tr[1]['avg_ns']/tt*100:.0f}% of the time).
 '''
     h5 = 2048*1025*8
     mlp = get('fftenkf::k7_spectral_mlp', 131072)
@@ -150,7 +150,7 @@ Each launch chain (one grid size, up to 40 filters: sweeps 1, 2 and 3) runs on o
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("summary", help="profile_summary.py's JSON")
-    ap.add_argument("bench", help="a bench.py JSON line from the same box (for the copy ceiling)")
+    ap.add_argument("bench", help="a bench.py JSON line from the same machine (for the copy ceiling)")
     ap.add_argument("outdir")
     args = ap.parse_args(argv)
     with open(args.summary) as f:
