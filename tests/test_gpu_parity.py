@@ -75,6 +75,8 @@ CASES = [
     (1024, 8, 5, np.float32, "scalar"),
     (512, 32, 8, np.float32, "spectral"),
     (512, 16, 6, np.float32, "scalar"),
+    (1024, 32, 23, np.float32, "scalar"),
+    (1024, 16, 7, np.float32, "spectral"),
 ]
 
 
